@@ -1,0 +1,154 @@
+"""Throughput of the LB-SMRT collide-and-stream step on one MI355X.
+
+Workload (default): 256^3 periodic box, D3Q343 (tensor product of the D1Q7
+rule r*{0,+-1,+-2,+-3}, degree 9), Hermite order N = 4, Kn = 0.05, Maxwellian
+perturbed by 16 random Fourier modes per field, FP32 state and contractions,
+FP64 conserved moments / frame shift / relaxation.
+
+Prints one JSON line: MLUPS (interior node updates per second / 1e6), the
+roofline of the step kernel (HBM bound: one FP32 read and one FP32 write of
+every population per node-step = 8 Q bytes), and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (abscissae, degree, N, box edge)
+    "box256_q343_n4": ([1, 2, 3], 9, 4, 256),
+    "box128_q343_n4": ([1, 2, 3], 9, 4, 128),
+    "box160_q729_n5": ([1, 2, 3, 5], 11, 5, 160),
+}
+
+TAU_STAR = {(2, 0): 1.0, (2, 1): 1.0, (3, 0): 2 / 3, (3, 1): 3 / 2, (4, 0): 432 / 763, (4, 1): 6 / 7,
+            (4, 2): 3 / 2, (5, 0): 864 / 1655, (5, 1): 108 / 163, (5, 2): 1.0}   # Table 4
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ab, deg, N, edge, kn, sample_edge=32, steps=12):
+    """The FP64 oracle on a sample_edge^3 box of the same Fourier workload
+    (same modes), `steps` steps; MLUPS scaled from that sample."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2401_11086_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    vs = O.make_velocity_set(ab, deg)
+    tau20 = kn * edge * vs.r
+    model = O.Model(vs=vs, N=N, tau={k: v * tau20 for k, v in TAU_STAR.items() if k[0] <= N}, shift=(0, 0, 0))
+    dom = O.Domain(nx=sample_edge, ny=sample_edge, nz=sample_edge, bc_x=0)
+    fields = W.fourier_box(sample_edge)
+    f = O.equilibrium_f(fields[0], fields[1:4], fields[4], model).reshape(vs.Q, sample_edge, sample_edge, sample_edge)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = O.step(f, model, dom)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(f).all()
+    return {"value": round(sample_edge ** 3 * steps / dt / 1e6, 6), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sample_edge}^3 periodic box of the same Fourier workload, {steps} steps, "
+                      f"{dt:.1f} s; numpy FP64 with {threads} BLAS threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="box256_q343_n4", choices=sorted(WORKLOADS))
+    ap.add_argument("--kn", type=float, default=0.05)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md but not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2401_11086_amd import Lattice
+    from paper_2401_11086_amd import workloads as W
+
+    ab, deg, N, edge = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    _progress(f"workload {args.workload}: building lattice")
+    r_guess = {9: 1.19697977039307, 11: 0.678003906334339}[deg]
+    tau20 = args.kn * edge * r_guess
+    tau = {k: v * tau20 for k, v in TAU_STAR.items() if k[0] <= N}
+    lat = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)])
+    assert abs(lat.c_l - r_guess) < 1e-12
+    fields = W.fourier_box_torch(edge, "cuda")
+    fa = lat.equilibrium(fields)
+    del fields
+    fb = lat.new_state()
+    torch.cuda.synchronize()
+    _progress(f"state ready: 2 x {fa.numel() * 4 / 1e9:.1f} GB; warmup {args.warmup}")
+    cur = lat.step(fa, fb, args.warmup) if args.warmup > 0 else fa
+    if cur is fb:
+        fa, fb = fb, fa
+    lat.sync()
+    _progress(f"timing {args.steps} steps")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    cur = lat.step(fa, fb, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.sync()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_step = gpu_ms / args.steps
+    nodes = lat.n_nodes
+    mlups = nodes * args.steps / (gpu_ms / 1e3) / 1e6
+    bytes_per_launch = 8.0 * lat.Q * nodes
+    achieved = bytes_per_launch / (ms_step / 1e3) / 1e9
+    _progress(f"{ms_step:.3f} ms/step, {mlups:.1f} MLUPS, {achieved:.0f} GB/s (wall {wall:.2f} s)")
+    rho = lat.moments(cur)[0]
+    assert torch.isfinite(rho).all() and abs(float(rho.mean()) - 1.0) < 1e-3
+
+    out = {
+        "metric": "MLUPS & % HBM/MFMA roofline, SMRT collide-stream; FP32 vs split-BF16; adjoint",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{edge}^3 periodic box, D3Q{lat.Q} (D1Q{lat.Q1} degree {deg}), Hermite N={N}, "
+                               f"Kn={args.kn}, 16 Fourier modes per field, FP32 state + FP64 moment section",
+                   "nodes": nodes, "Q": lat.Q, "M": lat.M, "precision": "fp32"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"k_collide_stream<{lat.Q1},{N}>", "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        _progress("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(ab, deg, N, edge, args.kn)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

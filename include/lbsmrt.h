@@ -1,0 +1,181 @@
+/*
+ * lbsmrt.h -- C ABI of the MI355X (gfx950) LB-SMRT collide-and-stream library.
+ *
+ * Method: Yan & Shan, "Lattice Boltzmann simulation of non-equilibrium flows
+ * using spectral multiple-relaxation-time collision model" (arXiv 2401.11086).
+ * One time step maps the post-collision populations f*_i(x) of every node to
+ * the next ones: pull-stream g_i(x) = f*_i(x - s_i) with s_i = e_i + k
+ * (Sec. 4.1, shifted stencil), project onto absolute Hermite moments (eq:an),
+ * shift them to the local frame (u, theta) by the binomial transform (Sec. 3),
+ * split each order n >= 2 into irreducible parts (App. A, eq:IrrDecomp), relax
+ * part (n,m) by 1/tau_bar_nm (eq:SMRT), shift back and rebuild
+ * f_i = w_i sum_alpha a_alpha He_alpha(c_i) / alpha!  (eq:fi with eq:hermite1's 1/n!).
+ *
+ * Conventions shared by every call:
+ *  - Velocity set: tensor product of a symmetric 1D integer stencil
+ *    {0, +-a_1, ..., +-a_p} scaled by the lattice constant c_l (Table 3).
+ *    Population index q = (ix*Q1 + iy)*Q1 + iz, where ix, iy, iz index the 1D
+ *    integers sorted ascending (-a_p, ..., 0, ..., a_p); Q = Q1^3.
+ *  - Hermite multi-indices alpha = (a,b,c), |alpha| <= N, ordered by order n,
+ *    then a descending, then b descending; M = (N+1)(N+2)(N+3)/6.
+ *  - Nodes: domains are concatenated; inside a domain node = x + nx*(y + ny*z).
+ *    Every f / lambda buffer is structure-of-arrays float32 [Q][f_stride]
+ *    (f_stride >= total nodes, a multiple of 64), owned by the caller, in
+ *    device memory.  Padding entries are never read or written.
+ *  - Units: time step 1, velocities in sqrt(k_B T_0), cell size c_l; theta is
+ *    the temperature over the reference temperature (validity needs
+ *    0 < theta < 2, Sec. 4.1).
+ *  - Streams: every call that touches the GPU enqueues its work on `stream`
+ *    (a hipStream_t; NULL = the default stream) and returns without waiting,
+ *    except lbsmrt_init_lattice and lbsmrt_sync_status, which wait.
+ *  - Errors: argument errors are returned synchronously.  A node found outside
+ *    the validity region (rho <= 0, theta <= 0, theta >= 2 or non-finite) sets
+ *    a device-side flag; it is reported by the next lbsmrt_sync_status.
+ *  - Threading: a context may be used from one host thread at a time.
+ */
+#ifndef LBSMRT_H
+#define LBSMRT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbsmrt_ctx lbsmrt_ctx;
+
+typedef enum {
+  LBSMRT_OK = 0,
+  LBSMRT_E_ARG = 1,          /* bad argument: null pointer, size, unsupported combination */
+  LBSMRT_E_QUADRATURE = 2,   /* no real positive-weight rule for the stencil and degree */
+  LBSMRT_E_STATE = 3,        /* a node left rho > 0, 0 < theta < 2, or became non-finite */
+  LBSMRT_E_HIP = 4,          /* a HIP runtime call failed */
+  LBSMRT_E_NOMEM = 5,        /* device or host allocation failed */
+  LBSMRT_E_UNSUPPORTED = 6   /* a (Q1, N) pair with no compiled kernel */
+} lbsmrt_status;
+
+typedef enum { LBSMRT_FP32 = 0, LBSMRT_SPLIT_BF16X3 = 1 } lbsmrt_precision;
+
+/* Velocity set and collision model (Sec. 4.2, Tables 3 and 4). */
+typedef struct {
+  int    n_abscissa;           /* p: number of positive 1D integers (3 for D1Q7, 4 for D1Q9) */
+  int    abscissa[16];         /* sorted distinct positive integers, e.g. {1,2,3} or {1,2,3,5} */
+  int    degree;               /* degree of exactness of the 1D rule (9 for D1Q7, 11 for D1Q9) */
+  int    order_N;              /* Hermite truncation N (4 or 5) */
+  int    shift_k[3];           /* integer frame shift: ubar = c_l * k (Sec. 4.1) */
+  double tau[6][3];            /* tau[n][m] in time steps at rho_ref, n = 2..N.  tau[2][1]
+                                  is ignored: the (2,1) part vanishes by the definition of theta. */
+  double rho_ref;              /* density at which tau[][] holds */
+  int    tau_density_scaling;  /* 1: tau_nm(x) = tau_nm * rho_ref / rho(x) (viscosity ~ theta) */
+  int    tau_offset_half;      /* 1: tau_bar = tau + 1/2 (trapezoidal discretisation); 0: tau_bar = tau */
+  int    regularized;          /* 1 (only value supported): f rebuilt from its M moments each step */
+  int    precision;            /* lbsmrt_precision of the projection/reconstruction contractions */
+} lbsmrt_lattice_desc;
+
+/* One domain.  bc_x = 0: periodic in x, y, z.  bc_x = 1: a shock tube whose
+ * x ends are held at the truncated Maxwellians of the (rho, u, theta) "in"
+ * (left) and "out" (right) states; y and z stay periodic (Sec. 4.2). */
+typedef struct {
+  int    nx, ny, nz;
+  int    bc_x;
+  double rho_in, u_in[3], theta_in;     /* lab-frame velocity */
+  double rho_out, u_out[3], theta_out;
+} lbsmrt_domain;
+
+/* Sizes of a context, filled by lbsmrt_get_info. */
+typedef struct {
+  int       Q, Q1, M, N;
+  double    c_l;               /* lattice constant r of the 1D rule */
+  double    w1d[17];           /* 1D weights in the sorted-ascending order of the stencil */
+  int       e1d[17];           /* 1D integers, sorted ascending */
+  long long n_nodes;           /* total nodes over all domains */
+  long long f_stride;          /* row stride of every [Q][f_stride] buffer */
+  long long f_len;             /* Q * f_stride floats per f or lambda buffer */
+  int       n_domains;
+  long long domain_offset[64]; /* first node of each domain (first 64 domains) */
+} lbsmrt_info;
+
+/* Build a context: solve the 1D quadrature (smallest positive-weight root),
+ * build Hermite and relaxation tables, upload them and the ghost-state
+ * equilibria of shock domains.  Waits for its own work on `stream`.
+ * Ownership: the context owns its device tables until lbsmrt_destroy.
+ * Errors: E_ARG (bad sizes, N outside 2..5, n_dom outside 1..4096),
+ * E_QUADRATURE, E_UNSUPPORTED (no kernel for this Q1 and N), E_HIP, E_NOMEM. */
+lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_domain* domains,
+                                  int n_domains, void* stream, lbsmrt_ctx** out);
+
+lbsmrt_status lbsmrt_get_info(const lbsmrt_ctx* ctx, lbsmrt_info* out);
+
+/* Advance n_steps >= 1 time steps (Sec. 3-4: stream, then SMRT collision).
+ * Step t reads buffer A if t is even, B if odd, and writes the other one, so
+ * after n_steps the state is in f_a if n_steps is even and in f_b if odd.
+ * f_a != f_b, both [Q][f_stride] float32 device buffers.  Asynchronous. */
+lbsmrt_status lbsmrt_step(lbsmrt_ctx* ctx, float* f_a, float* f_b, int n_steps, void* stream);
+
+/* Moment fields of the pre-collision populations of state f (stream first),
+ * the quantities plotted in Sec. 4.3.  out is float64 [rows][n_nodes] in
+ * device memory; the rows of each selected group follow in bit order:
+ *   LBSMRT_MOM_BASIC  5 rows: rho, u_x, u_y, u_z (lab frame), theta
+ *   LBSMRT_MOM_SIGMA  6 rows: sigma = theta d^(2), components xx,xy,xz,yy,yz,zz
+ *   LBSMRT_MOM_Q      3 rows: q = theta^(3/2)/2 tr d^(3)
+ *   LBSMRT_MOM_M3    10 rows: m = d^(3,0)/D(3,0) in multi-index order
+ *   LBSMRT_MOM_R41    6 rows: R^(4,1) = d^(4,1)/D(4,1) (needs N >= 4)
+ *   LBSMRT_MOM_R42    1 row : R^(4,2) = d^(4,2)/D(4,2) (needs N >= 4)
+ *   LBSMRT_MOM_DLOCAL M rows: local-frame moments d_beta (rho absorbed)
+ *   LBSMRT_MOM_ALAB   M rows: lattice-frame moments a_alpha (eq:an)
+ * lbsmrt_moment_rows gives the row count of a mask.  Asynchronous. */
+enum {
+  LBSMRT_MOM_BASIC = 1u, LBSMRT_MOM_SIGMA = 2u, LBSMRT_MOM_Q = 4u, LBSMRT_MOM_M3 = 8u,
+  LBSMRT_MOM_R41 = 16u, LBSMRT_MOM_R42 = 32u, LBSMRT_MOM_DLOCAL = 64u, LBSMRT_MOM_ALAB = 128u
+};
+lbsmrt_status lbsmrt_moments(lbsmrt_ctx* ctx, const float* f, double* out, unsigned fields_mask,
+                             void* stream);
+int lbsmrt_moment_rows(const lbsmrt_ctx* ctx, unsigned fields_mask);
+
+/* Truncated discrete Maxwellian f_i = w_i sum_alpha a^eq_alpha He_alpha(c_i)/alpha!
+ * with a^eq_alpha = rho prod_k A_{alpha_k}(u_k - ubar_k, theta) (App. B closed form).
+ * fields: float64 [5][n_nodes] device rows rho, u_x, u_y, u_z (lab frame), theta.
+ * f: [Q][f_stride] float32 device buffer written for every node.  Asynchronous. */
+lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* ctx, const double* fields, float* f, void* stream);
+
+/* Adjoint of one step f_{t+1} = Step(f_t; tau) (reverse mode of the same
+ * stream + collision).  Given lam_next = dL/df_{t+1} it writes
+ * lam_t = (df_{t+1}/df_t)^T lam_next and adds (d f_{t+1}/d tau_nm)^T lam_next
+ * to dL_dtau[n][m] (float64 [6][3] in device memory, accumulated, fixed
+ * summation order so results are reproducible).  f_t, lam_next, lam_t are
+ * [Q][f_stride] float32 device buffers; lam_t must not alias the others.
+ * Asynchronous. */
+lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* ctx, const float* f_t, const float* lam_next,
+                                  float* lam_t, double* dL_dtau, void* stream);
+
+/* Seed of the adjoint for the shock-profile misfit
+ *   L = sum_x [ s_rho^2 (rho - rho*)^2 + s_theta^2 (theta - theta*)^2 + s_q^2 (q_x - q_x*)^2 ]
+ * of the pre-collision moments of state f.  target: float64 [3][n_nodes] device
+ * rows rho*, theta*, q_x*; scales: host [3].  Writes lam = dL/df ([Q][f_stride])
+ * and L into *loss (float64, device).  Asynchronous. */
+lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* ctx, const float* f, const double* target,
+                               const double* scales, float* lam, double* loss, void* stream);
+
+/* Wait for `stream` and report (and clear) the latched device state flag. */
+lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* ctx, void* stream);
+
+void lbsmrt_destroy(lbsmrt_ctx* ctx);
+const char* lbsmrt_status_string(lbsmrt_status s);
+
+/* ---- host-only helpers (no GPU) --------------------------------------- */
+
+/* 1D rule r*{0, +-a_1..a_p} exact to `degree` for the unit Gaussian: writes
+ * r and the p+1 weights (w_0, w_{a_1}, ..., w_{a_p}).  Smallest positive-weight
+ * root (Table 3).  E_QUADRATURE if none exists, E_ARG on bad input. */
+lbsmrt_status lbsmrt_solve_quadrature(int n_abscissa, const int* abscissa, int degree,
+                                      double* r_out, double* w_out);
+
+/* Normal-shock end states (eq:rankine, temperature ratio with Ma^2 in the
+ * denominator, which is what reproduces Table 3), rho1 = 1.  Pass theta1 > 0,
+ * or theta1 <= 0 and theta2 > 0.  out[8] = rho1, u1, theta1, rho2, u2, theta2,
+ * (u1+u2)/2, and k = round(((u1+u2)/2)/c_l) as a double (if c_l > 0). */
+lbsmrt_status lbsmrt_shock_states(double Ma, double gamma, double theta1, double theta2,
+                                  double c_l, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBSMRT_H */

@@ -1,0 +1,133 @@
+// Host-side set-up of the LB-SMRT lattice: the 1D quadrature (Sec. 4.2,
+// D1Qd rules and Table 3's lattice constants) and the normal-shock end
+// states (eq:rankine).  Plain C++, long double, no GPU.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lbsmrt.h"
+#include "host_setup.hpp"
+
+namespace lbsmrt {
+
+namespace {
+
+long double gaussian_even_moment(int k) {  // (2k-1)!!
+  long double m = 1.0L;
+  for (int j = 1; j < 2 * k; j += 2) m *= j;
+  return m;
+}
+
+// Weights w_0, w_{a_j} matching the even moments 0..2(n_eq-1) for a given r;
+// Gaussian elimination with partial pivoting.  Returns false if singular.
+bool weights_for(const std::vector<int>& ab, long double r, int n_eq, std::vector<long double>& w) {
+  const int p = static_cast<int>(ab.size());
+  const int n = p + 1;
+  std::vector<long double> A(n_eq * n), b(n_eq);
+  for (int k = 0; k < n_eq; ++k) {
+    A[k * n + 0] = (k == 0) ? 1.0L : 0.0L;
+    for (int j = 0; j < p; ++j) A[k * n + j + 1] = 2.0L * powl(ab[j] * r, 2 * k);
+    b[k] = gaussian_even_moment(k);
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < n; ++i)
+      if (fabsl(A[i * n + c]) > fabsl(A[piv * n + c])) piv = i;
+    if (A[piv * n + c] == 0.0L) return false;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(A[c * n + j], A[piv * n + j]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int i = c + 1; i < n; ++i) {
+      const long double f = A[i * n + c] / A[c * n + c];
+      for (int j = c; j < n; ++j) A[i * n + j] -= f * A[c * n + j];
+      b[i] -= f * b[c];
+    }
+  }
+  w.assign(n, 0.0L);
+  for (int i = n - 1; i >= 0; --i) {
+    long double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * w[j];
+    w[i] = s / A[i * n + i];
+  }
+  return true;
+}
+
+bool residual(const std::vector<int>& ab, long double r, int k_top, long double& res) {
+  std::vector<long double> w;
+  if (!weights_for(ab, r, k_top, w)) return false;
+  long double s = 0.0L;
+  for (size_t j = 0; j < ab.size(); ++j) s += 2.0L * w[j + 1] * powl(ab[j] * r, 2 * k_top);
+  res = s - gaussian_even_moment(k_top);
+  return true;
+}
+
+}  // namespace
+
+lbsmrt_status solve_quadrature(const int* abscissa, int p, int degree, double* r_out, double* w_out) {
+  if (p < 1 || p > 16 || !abscissa || !r_out || !w_out) return LBSMRT_E_ARG;
+  std::vector<int> ab(abscissa, abscissa + p);
+  for (int j = 0; j < p; ++j) {
+    if (ab[j] <= 0) return LBSMRT_E_ARG;
+    if (j > 0 && ab[j] <= ab[j - 1]) return LBSMRT_E_ARG;
+  }
+  // p+1 weights and r are fixed by the p+2 even moments 0..2(p+1)
+  if (degree / 2 + 1 != p + 2) return LBSMRT_E_QUADRATURE;
+  const int k_top = p + 1;
+  const int n_grid = 12000;
+  const long double lo = 0.02L, hi = 6.0L;
+  long double prev_r = lo, prev_f = 0.0L;
+  bool have_prev = residual(ab, lo, k_top, prev_f);
+  for (int i = 1; i < n_grid; ++i) {
+    const long double r = lo + (hi - lo) * i / (n_grid - 1);
+    long double f;
+    if (!residual(ab, r, k_top, f)) { have_prev = false; continue; }
+    if (have_prev && ((prev_f < 0) != (f < 0))) {
+      long double a = prev_r, b = r, fa = prev_f;
+      for (int it = 0; it < 200; ++it) {
+        const long double m = 0.5L * (a + b);
+        long double fm;
+        if (!residual(ab, m, k_top, fm)) break;
+        if ((fm < 0) == (fa < 0)) { a = m; fa = fm; } else { b = m; }
+      }
+      const long double root = 0.5L * (a + b);
+      std::vector<long double> w;
+      if (weights_for(ab, root, k_top, w)) {
+        bool pos = true;
+        for (long double x : w) pos = pos && (x > 0.0L);
+        if (pos) {
+          *r_out = static_cast<double>(root);
+          for (int j = 0; j <= p; ++j) w_out[j] = static_cast<double>(w[j]);
+          return LBSMRT_OK;
+        }
+      }
+    }
+    prev_r = r;
+    prev_f = f;
+    have_prev = true;
+  }
+  return LBSMRT_E_QUADRATURE;
+}
+
+lbsmrt_status shock_states(double Ma, double gamma, double theta1, double theta2, double c_l, double* out) {
+  if (!out || !(Ma >= 1.0) || !(gamma > 1.0)) return LBSMRT_E_ARG;
+  const double M2 = Ma * Ma;
+  const double dens = (gamma + 1.0) * M2 / ((gamma - 1.0) * M2 + 2.0);
+  const double tratio = (2.0 * gamma * M2 - gamma + 1.0) * ((gamma - 1.0) * M2 + 2.0) /
+                        ((gamma + 1.0) * (gamma + 1.0) * M2);
+  if (!(theta1 > 0.0)) {
+    if (!(theta2 > 0.0)) return LBSMRT_E_ARG;
+    theta1 = theta2 / tratio;
+  }
+  theta2 = theta1 * tratio;
+  const double u1 = Ma * std::sqrt(gamma * theta1);
+  const double u2 = u1 / dens;
+  const double umid = 0.5 * (u1 + u2);
+  out[0] = 1.0; out[1] = u1; out[2] = theta1;
+  out[3] = dens; out[4] = u2; out[5] = theta2;
+  out[6] = umid;
+  out[7] = (c_l > 0.0) ? std::floor(umid / c_l + 0.5) : 0.0;
+  return LBSMRT_OK;
+}
+
+}  // namespace lbsmrt

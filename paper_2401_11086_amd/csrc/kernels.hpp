@@ -1,0 +1,434 @@
+// gfx950 kernels of the LB-SMRT step: fused pull-stream + SMRT collision,
+// moments, equilibrium fill.  One work-item per lattice node; the f state is
+// structure-of-arrays float32 [Q][stride], so for every population q the
+// 64 lanes of a wave touch 64 consecutive nodes (coalesced 256-byte rows).
+// The projection and reconstruction contractions are sum-factorised over the
+// tensor-product velocity set (x, then y, then z), FP32 FMA with the 1D
+// Hermite tables held in scalar registers; the conserved sums, the frame
+// shift, the irreducible split and the relaxation run in FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "smrt_node.hpp"
+
+namespace lbsmrt {
+
+struct DomainDev {
+  long long off;      // first node of the domain in the global node space
+  int nx, ny, nz;
+  int bc_x;           // 0 periodic, 1 fixed Maxwellian ends
+  int ghost;          // column of the left ghost state in the ghost table (right = ghost+1)
+  int pad;
+};
+
+struct BlockDev {
+  int dom;            // domain handled by this work-group
+  int first;          // first local node of the work-group
+};
+
+struct StepArgs {
+  const DomainDev* doms;
+  const BlockDev* blocks;
+  const float* ghosts;       // [Q][n_ghost]
+  int n_ghost;
+  long long stride;
+  int* err;
+};
+
+enum : int { kErrState = 1 };
+
+// Loads and stores at a wave-uniform base plus a 32-bit byte offset, so the
+// compiler can use the scalar-base (saddr) form of global memory instructions.
+__device__ __forceinline__ float load_at(const float* __restrict__ base, unsigned byte_off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void store_at(float* __restrict__ base, unsigned byte_off, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+template <int Q1, int N>
+struct Shape {
+  static constexpr int M = n_moments(N);
+  static constexpr int P2 = n_sym(N);
+  static constexpr int Q = Q1 * Q1 * Q1;
+};
+
+// Node coordinates and source offsets of the pull stream g_i(x) = f*_i(x - e_i - k).
+template <int Q1>
+struct Pull {
+  int node;                  // global node index of this work-item
+  int row;                   // global node index of (x = 0, y, z) of this work-item
+  int x, nx, bc_x;
+  unsigned yo[Q1];           // byte offset of source row ys*nx per iy
+  unsigned zo[Q1];           // byte offset of source plane zs*nx*ny per iz
+  int gcol;                  // left ghost column
+};
+
+template <int Q1>
+__device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs& A, Pull<Q1>& P) {
+  const BlockDev bd = A.blocks[blockIdx.x];
+  const DomainDev D = A.doms[bd.dom];
+  const int local = bd.first + static_cast<int>(threadIdx.x);
+  const int nxy = D.nx * D.ny;
+  if (local >= nxy * D.nz) return false;
+  const int x = local % D.nx;
+  const int y = (local / D.nx) % D.ny;
+  const int z = local / nxy;
+  P.node = static_cast<int>(D.off) + local;
+  P.row = static_cast<int>(D.off);
+  P.x = x;
+  P.nx = D.nx;
+  P.bc_x = D.bc_x;
+  P.gcol = D.ghost;
+#pragma unroll
+  for (int j = 0; j < Q1; ++j) {
+    int t = (y - (L.e[j] + L.k[1])) % D.ny;
+    P.yo[j] = static_cast<unsigned>((t < 0 ? t + D.ny : t) * D.nx) * 4u;
+    t = (z - (L.e[j] + L.k[2])) % D.nz;
+    P.zo[j] = static_cast<unsigned>((t < 0 ? t + D.nz : t) * nxy) * 4u;
+  }
+  return true;
+}
+
+// Source x of population column ix: >= 0 inside, -1 / -2 for the left / right ghost.
+template <int Q1>
+__device__ __forceinline__ int source_x(const LatticeConst& L, const Pull<Q1>& P, int ix) {
+  int xs = P.x - (L.e[ix] + L.k[0]);
+  if (P.bc_x == 0) {
+    xs %= P.nx;
+    if (xs < 0) xs += P.nx;
+    return xs;
+  }
+  return xs < 0 ? -1 : (xs >= P.nx ? -2 : xs);
+}
+
+// Gather the streamed populations and project them (eq:an), sum-factorised:
+//   a[ax,ay,az] = sum_ix He_ax(c_ix) sum_iy He_ay(c_iy) sum_iz He_az(c_iz) g[ix,iy,iz]
+// plus FP64 sums S = (sum g, sum g e_x, sum g e_y, sum g e_z, sum g |e|^2).
+// The x loop stays rolled (one 2D slab of Q1*Q1 populations per iteration).
+template <int Q1, int N, bool SHOCK>
+__device__ __forceinline__ void gather_project(const LatticeConst& L, const StepArgs& A,
+                                               const float* __restrict__ f, const Pull<Q1>& P,
+                                               float (&a)[Shape<Q1, N>::M], double (&S)[5]) {
+  constexpr int P2 = Shape<Q1, N>::P2;
+#pragma unroll
+  for (int i = 0; i < Shape<Q1, N>::M; ++i) a[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) S[i] = 0.0;
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    float t2[P2];
+#pragma unroll
+    for (int i = 0; i < P2; ++i) t2[i] = 0.f;
+    double U0 = 0.0, U1y = 0.0, U1z = 0.0, U2 = 0.0;
+    const int xs = source_x<Q1>(L, P, ix);
+    const float* __restrict__ fx = f + static_cast<size_t>(ix * Q1 * Q1) * A.stride;
+    const unsigned xoff = static_cast<unsigned>(P.row + xs) * 4u;
+    // issue the whole slab of Q1*Q1 loads before any use (memory-level parallelism)
+    float gs[Q1 * Q1];
+#pragma unroll
+    for (int iy = 0; iy < Q1; ++iy) {
+      const unsigned xyoff = xoff + P.yo[iy];
+#pragma unroll
+      for (int iz = 0; iz < Q1; ++iz) {
+        const int qs = iy * Q1 + iz;   // population inside the slab
+        if constexpr (SHOCK) {
+          if (xs >= 0) {
+            gs[qs] = load_at(fx + static_cast<size_t>(qs) * A.stride, xyoff + P.zo[iz]);
+          } else {
+            gs[qs] = A.ghosts[static_cast<size_t>(ix * Q1 * Q1 + qs) * A.n_ghost + P.gcol + (xs == -1 ? 0 : 1)];
+          }
+        } else {
+          gs[qs] = load_at(fx + static_cast<size_t>(qs) * A.stride, xyoff + P.zo[iz]);
+        }
+      }
+    }
+#pragma unroll
+    for (int iy = 0; iy < Q1; ++iy) {
+      float t1[N + 1];
+#pragma unroll
+      for (int n = 0; n <= N; ++n) t1[n] = 0.f;
+      double V0 = 0.0, V1 = 0.0, V2 = 0.0;
+#pragma unroll
+      for (int iz = 0; iz < Q1; ++iz) {
+        const float g = gs[iy * Q1 + iz];
+#pragma unroll
+        for (int n = 0; n <= N; ++n) t1[n] = fmaf(g, L.He[iz][n], t1[n]);
+        const double gd = static_cast<double>(g);
+        const double ez = static_cast<double>(L.e[iz]);
+        V0 += gd;
+        V1 = fma(gd, ez, V1);
+        V2 = fma(gd, ez * ez, V2);
+      }
+#pragma unroll
+      for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+        for (int az = 0; az <= N; ++az)
+          if (ay + az <= N) t2[pair_pos(ay, az)] = fmaf(t1[az], L.He[iy][ay], t2[pair_pos(ay, az)]);
+      const double ey = static_cast<double>(L.e[iy]);
+      U0 += V0;
+      U1y = fma(V0, ey, U1y);
+      U1z += V1;
+      U2 += fma(V0, ey * ey, V2);
+    }
+    float hx[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) hx[n] = L.He[ix][n];
+#pragma unroll
+    for (int ax = 0; ax <= N; ++ax)
+#pragma unroll
+      for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+        for (int az = 0; az <= N; ++az)
+          if (ax + ay + az <= N) a[midx(ax, ay, az)] = fmaf(t2[pair_pos(ay, az)], hx[ax], a[midx(ax, ay, az)]);
+    const double ex = static_cast<double>(L.e[ix]);
+    S[0] += U0;
+    S[1] = fma(U0, ex, S[1]);
+    S[2] += U1y;
+    S[3] += U1z;
+    S[4] += fma(U0, ex * ex, U2);
+  }
+}
+
+// Conserved moments -> rho, u' (relative to ubar), theta; validity (Sec. 4.1).
+struct Macro {
+  double rho, ux, uy, uz, th;
+};
+
+__device__ __forceinline__ Macro macro_from_sums(const LatticeConst& L, const double (&S)[5], int* err) {
+  Macro m;
+  m.rho = S[0];
+  const double inv = 1.0 / m.rho;
+  m.ux = L.r * S[1] * inv;
+  m.uy = L.r * S[2] * inv;
+  m.uz = L.r * S[3] * inv;
+  const double E = L.r * L.r * S[4];
+  m.th = (E * inv - (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz)) * (1.0 / 3.0);
+  if (!(m.rho > 0.0 && m.th > 0.0 && m.th < 2.0)) atomicOr(err, kErrState);
+  return m;
+}
+
+// a (lattice frame, FP32 projection) -> d (local frame, FP64), rho absorbed:
+//   d_beta = theta^{-|beta|/2} sum_{gamma <= beta} prod_k C(beta_k, gamma_k) B_{beta_k - gamma_k} a_gamma
+template <int N>
+__device__ __forceinline__ void to_local(double* d, const Macro& m) {
+  double Bx[N + 1], By[N + 1], Bz[N + 1];
+  shift_poly<N>(-m.ux, 1.0 - m.th, Bx);
+  shift_poly<N>(-m.uy, 1.0 - m.th, By);
+  shift_poly<N>(-m.uz, 1.0 - m.th, Bz);
+  axis_transform<N, 0>(d, Bx);
+  axis_transform<N, 1>(d, By);
+  axis_transform<N, 2>(d, Bz);
+  scale_by_order<N>(d, 1.0 / sqrt(m.th));
+  d[0] = m.rho;
+  d[1] = 0.0;
+  d[2] = 0.0;
+  d[3] = 0.0;
+}
+
+// d (local) -> a (lattice):  a_alpha = sum_{beta <= alpha} prod_k C(alpha_k, beta_k) A_{alpha_k - beta_k} theta^{|beta|/2} d_beta
+template <int N>
+__device__ __forceinline__ void to_lattice(double* d, const Macro& m) {
+  double Ax[N + 1], Ay[N + 1], Az[N + 1];
+  scale_by_order<N>(d, sqrt(m.th));
+  shift_poly<N>(m.ux, m.th - 1.0, Ax);
+  shift_poly<N>(m.uy, m.th - 1.0, Ay);
+  shift_poly<N>(m.uz, m.th - 1.0, Az);
+  axis_transform<N, 0>(d, Ax);
+  axis_transform<N, 1>(d, Ay);
+  axis_transform<N, 2>(d, Az);
+}
+
+// eq:SMRT with tau_nm(x) = tau_nm * (rho_ref / rho) [optional] and tau_bar = tau + offset.
+template <int N>
+__device__ __forceinline__ void relax(double* d, const LatticeConst& L, double rho) {
+  const double sc = L.density_scaling ? L.rho_ref / rho : 1.0;
+#pragma unroll
+  for (int n = 2; n <= N; ++n) {
+    double om[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) om[m] = (2 * m <= n) ? 1.0 / fma(L.tau[n][m], sc, L.tau_offset) : 0.0;
+    if (n == 2) om[1] = 0.0;   // the (2,1) part is zero by the definition of theta
+    double* dn = d + order_start(n);
+    if (n == 2) relax_order<2>(dn, om);
+    if (n == 3) relax_order<3>(dn, om);
+    if constexpr (N >= 4) if (n == 4) relax_order<4>(dn, om);
+    if constexpr (N >= 5) if (n == 5) relax_order<5>(dn, om);
+  }
+}
+
+// Reconstruction (eq:fi with 1/alpha!), sum-factorised, and store to the own node.
+template <int Q1, int N>
+__device__ __forceinline__ void reconstruct_store(const LatticeConst& L, const float (&ap)[Shape<Q1, N>::M],
+                                                  float* __restrict__ out, long long stride, int node) {
+  constexpr int P2 = Shape<Q1, N>::P2;
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    float rx[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) rx[n] = L.Rw[ix][n];
+    float u2[P2];
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        if (ay + az > N) continue;
+        float s = 0.f;
+#pragma unroll
+        for (int ax = 0; ax <= N; ++ax)
+          if (ax + ay + az <= N) s = fmaf(ap[midx(ax, ay, az)], rx[ax], s);
+        u2[pair_pos(ay, az)] = s;
+      }
+#pragma unroll
+    for (int iy = 0; iy < Q1; ++iy) {
+      float v[N + 1];
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        float s = 0.f;
+#pragma unroll
+        for (int ay = 0; ay <= N; ++ay)
+          if (ay + az <= N) s = fmaf(u2[pair_pos(ay, az)], L.Rw[iy][ay], s);
+        v[az] = s;
+      }
+#pragma unroll
+      for (int iz = 0; iz < Q1; ++iz) {
+        float s = 0.f;
+#pragma unroll
+        for (int az = 0; az <= N; ++az) s = fmaf(v[az], L.Rw[iz][az], s);
+        const int q = (ix * Q1 + iy) * Q1 + iz;
+        store_at(out + static_cast<size_t>(q) * stride, static_cast<unsigned>(node) * 4u, s);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <int Q1, int N, bool SHOCK>
+__global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
+                                                        float* __restrict__ fdst) {
+  constexpr int M = Shape<Q1, N>::M;
+  Pull<Q1> P;
+  if (!make_pull<Q1>(L, A, P)) return;
+  float a[M];
+  double S[5];
+  gather_project<Q1, N, SHOCK>(L, A, fsrc, P, a, S);
+  const Macro mac = macro_from_sums(L, S, A.err);
+  double d[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a[i]);
+  d[0] = S[0];            // orders 0 and 1 from the FP64 sums
+  d[1] = L.r * S[1];
+  d[2] = L.r * S[2];
+  d[3] = L.r * S[3];
+  to_local<N>(d, mac);
+  relax<N>(d, L, mac.rho);
+  to_lattice<N>(d, mac);
+  float ap[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) ap[i] = static_cast<float>(d[i]);
+  reconstruct_store<Q1, N>(L, ap, fdst, A.stride, P.node);
+}
+
+// Moment fields of the pre-collision populations (see lbsmrt_moments).
+template <int Q1, int N, bool SHOCK>
+__global__ __launch_bounds__(256) void k_moments(LatticeConst L, StepArgs A, const float* __restrict__ f,
+                                                 double* __restrict__ out, unsigned mask, long long n_nodes) {
+  constexpr int M = Shape<Q1, N>::M;
+  Pull<Q1> P;
+  if (!make_pull<Q1>(L, A, P)) return;
+  float a[M];
+  double S[5];
+  gather_project<Q1, N, SHOCK>(L, A, f, P, a, S);
+  const Macro mac = macro_from_sums(L, S, A.err);
+  double aa[M], d[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) aa[i] = static_cast<double>(a[i]);
+  aa[0] = S[0];
+  aa[1] = L.r * S[1];
+  aa[2] = L.r * S[2];
+  aa[3] = L.r * S[3];
+#pragma unroll
+  for (int i = 0; i < M; ++i) d[i] = aa[i];
+  to_local<N>(d, mac);
+  double* o = out + P.node;
+  long long row = 0;
+  auto put = [&](double v) { o[row * n_nodes] = v; ++row; };
+  if (mask & 1u) {
+    put(mac.rho);
+    put(L.r * L.k[0] + mac.ux);
+    put(L.r * L.k[1] + mac.uy);
+    put(L.r * L.k[2] + mac.uz);
+    put(mac.th);
+  }
+  if (mask & 2u) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) put(mac.th * d[order_start(2) + i]);
+  }
+  if (mask & 4u) {
+    double t[3];
+    sym_trace<1>(d + order_start(3), t);
+    const double c = 0.5 * mac.th * sqrt(mac.th);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) put(c * t[i]);
+  }
+  if (mask & 8u) {
+    double p[10];
+    irreducible_part<3, 0>(d + order_start(3), p);
+    constexpr double inv = 1.0 / coefD(3, 0);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) put(p[i] * inv);
+  }
+  if constexpr (N >= 4) {
+    if (mask & 16u) {
+      double p[6];
+      irreducible_part<4, 1>(d + order_start(4), p);
+      constexpr double inv = 1.0 / coefD(4, 1);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) put(p[i] * inv);
+    }
+    if (mask & 32u) {
+      double p[1];
+      irreducible_part<4, 2>(d + order_start(4), p);
+      put(p[0] * (1.0 / coefD(4, 2)));
+    }
+  }
+  if (mask & 64u) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) put(d[i]);
+  }
+  if (mask & 128u) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) put(aa[i]);
+  }
+}
+
+// Truncated Maxwellian of lab-frame (rho, u, theta) rows; nodes 0..count-1 map to
+// columns 0..count-1 of f (row stride `stride`).
+template <int Q1, int N>
+__global__ __launch_bounds__(256) void k_equilibrium(LatticeConst L, const double* __restrict__ fields, long long count,
+                                                     float* __restrict__ f, long long stride) {
+  constexpr int M = Shape<Q1, N>::M;
+  const long long node = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (node >= count) return;
+  const double rho = fields[node];
+  const double ux = fields[count + node] - L.r * L.k[0];
+  const double uy = fields[2 * count + node] - L.r * L.k[1];
+  const double uz = fields[3 * count + node] - L.r * L.k[2];
+  const double th = fields[4 * count + node];
+  double Ax[N + 1], Ay[N + 1], Az[N + 1];
+  shift_poly<N>(ux, th - 1.0, Ax);
+  shift_poly<N>(uy, th - 1.0, Ay);
+  shift_poly<N>(uz, th - 1.0, Az);
+  float a[M];
+#pragma unroll
+  for (int ax = 0; ax <= N; ++ax)
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az)
+        if (ax + ay + az <= N) a[midx(ax, ay, az)] = static_cast<float>(rho * Ax[ax] * Ay[ay] * Az[az]);
+  reconstruct_store<Q1, N>(L, a, f, stride, static_cast<int>(node));
+}
+
+}  // namespace lbsmrt

@@ -1,0 +1,368 @@
+// C-ABI of the LB-SMRT library: context set-up, launches, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "host_setup.hpp"
+#include "kernels.hpp"
+#include "lbsmrt.h"
+
+using namespace lbsmrt;
+
+struct lbsmrt_ctx {
+  int device = -1;
+  int Q1 = 0, N = 0, Q = 0, M = 0;
+  double r = 0.0;
+  double w1[17] = {};
+  int e1[17] = {};
+  LatticeConst L{};
+  std::vector<lbsmrt_domain> doms;
+  std::vector<long long> dom_off;
+  long long n_nodes = 0, stride = 0;
+  bool shock = false;
+  int block = 256;
+  int n_blocks = 0;
+  int n_ghost = 0;
+  DomainDev* d_doms = nullptr;
+  BlockDev* d_blocks = nullptr;
+  float* d_ghost = nullptr;
+  double* d_ghost_fields = nullptr;
+  int* d_err = nullptr;
+  int precision = LBSMRT_FP32;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e__ = (expr);                           \
+    if (e__ != hipSuccess) return LBSMRT_E_HIP;        \
+  } while (0)
+
+double hermite_1d(int n, double x) {
+  double h0 = 1.0, h1 = x;
+  if (n == 0) return h0;
+  for (int k = 1; k < n; ++k) {
+    const double h2 = x * h1 - k * h0;
+    h0 = h1;
+    h1 = h2;
+  }
+  return h1;
+}
+
+// Launch dispatch over the compiled (Q1, N) pairs.
+template <int Q1, int N>
+struct Launch {
+  static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
+    if (c->shock)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src, dst);
+    else
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src, dst);
+  }
+  static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s) {
+    if (c->shock)
+      hipLaunchKernelGGL((k_moments<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, out, mask,
+                         c->n_nodes);
+    else
+      hipLaunchKernelGGL((k_moments<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, out, mask,
+                         c->n_nodes);
+  }
+  static void equilibrium(lbsmrt_ctx* c, const double* fields, long long count, float* f, long long stride,
+                          hipStream_t s) {
+    const int bs = 256;
+    const long long nb = (count + bs - 1) / bs;
+    hipLaunchKernelGGL((k_equilibrium<Q1, N>), dim3(static_cast<unsigned>(nb)), dim3(bs), 0, s, c->L, fields, count,
+                       f, stride);
+  }
+};
+
+bool supported(int Q1, int N) { return (Q1 == 7 && (N == 3 || N == 4)) || (Q1 == 9 && (N == 4 || N == 5)); }
+
+template <typename F>
+void dispatch(int Q1, int N, F&& fn) {
+  if (Q1 == 7 && N == 3) fn(Launch<7, 3>{});
+  else if (Q1 == 7 && N == 4) fn(Launch<7, 4>{});
+  else if (Q1 == 9 && N == 4) fn(Launch<9, 4>{});
+  else if (Q1 == 9 && N == 5) fn(Launch<9, 5>{});
+}
+
+StepArgs step_args(const lbsmrt_ctx* c) {
+  StepArgs A;
+  A.doms = c->d_doms;
+  A.blocks = c->d_blocks;
+  A.ghosts = c->d_ghost;
+  A.n_ghost = c->n_ghost;
+  A.stride = c->stride;
+  A.err = c->d_err;
+  return A;
+}
+
+void free_ctx(lbsmrt_ctx* c) {
+  if (!c) return;
+  if (c->device >= 0) (void)hipSetDevice(c->device);
+  (void)hipFree(c->d_doms);
+  (void)hipFree(c->d_blocks);
+  (void)hipFree(c->d_ghost);
+  (void)hipFree(c->d_ghost_fields);
+  (void)hipFree(c->d_err);
+  delete c;
+}
+
+lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
+  if (!d) return LBSMRT_E_ARG;
+  if (d->n_abscissa < 1 || d->n_abscissa > 8) return LBSMRT_E_ARG;
+  if (d->order_N < 2 || d->order_N > kMaxN) return LBSMRT_E_ARG;
+  if (d->regularized != 1) return LBSMRT_E_UNSUPPORTED;
+  if (d->precision != LBSMRT_FP32) return LBSMRT_E_UNSUPPORTED;
+  if (!(d->rho_ref > 0.0)) return LBSMRT_E_ARG;
+  for (int n = 2; n <= d->order_N; ++n)
+    for (int m = 0; 2 * m <= n; ++m) {
+      if (n == 2 && m == 1) continue;
+      if (!(d->tau[n][m] > 0.0) || !std::isfinite(d->tau[n][m])) return LBSMRT_E_ARG;
+    }
+  return LBSMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbsmrt_status_string(lbsmrt_status s) {
+  switch (s) {
+    case LBSMRT_OK: return "ok";
+    case LBSMRT_E_ARG: return "invalid argument";
+    case LBSMRT_E_QUADRATURE: return "no positive-weight quadrature for this stencil and degree";
+    case LBSMRT_E_STATE: return "a node left rho > 0, 0 < theta < 2 (or became non-finite)";
+    case LBSMRT_E_HIP: return "HIP runtime error";
+    case LBSMRT_E_NOMEM: return "out of memory";
+    case LBSMRT_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+lbsmrt_status lbsmrt_solve_quadrature(int n_abscissa, const int* abscissa, int degree, double* r_out, double* w_out) {
+  return solve_quadrature(abscissa, n_abscissa, degree, r_out, w_out);
+}
+
+lbsmrt_status lbsmrt_shock_states(double Ma, double gamma, double theta1, double theta2, double c_l, double* out) {
+  return shock_states(Ma, gamma, theta1, theta2, c_l, out);
+}
+
+lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_domain* domains, int n_domains,
+                                  void* stream, lbsmrt_ctx** out) {
+  if (!out || !domains || n_domains < 1 || n_domains > 4096) return LBSMRT_E_ARG;
+  *out = nullptr;
+  lbsmrt_status st = validate_desc(desc);
+  if (st != LBSMRT_OK) return st;
+  const int p = desc->n_abscissa;
+  const int Q1 = 2 * p + 1;
+  if (!supported(Q1, desc->order_N)) return LBSMRT_E_UNSUPPORTED;
+
+  double r = 0.0, w[17] = {};
+  st = solve_quadrature(desc->abscissa, p, desc->degree, &r, w);
+  if (st != LBSMRT_OK) return st;
+  if (desc->degree < 2 * desc->order_N) return LBSMRT_E_ARG;  // eq:an needs a degree-2N rule
+
+  lbsmrt_ctx* c = new (std::nothrow) lbsmrt_ctx();
+  if (!c) return LBSMRT_E_NOMEM;
+  c->Q1 = Q1;
+  c->N = desc->order_N;
+  c->Q = Q1 * Q1 * Q1;
+  c->M = n_moments(c->N);
+  c->r = r;
+  c->precision = desc->precision;
+  for (int j = 0; j < Q1; ++j) {
+    const int jj = j - p;  // -p..p
+    const int a = jj == 0 ? 0 : (jj < 0 ? -desc->abscissa[-jj - 1] : desc->abscissa[jj - 1]);
+    c->e1[j] = a;
+    c->w1[j] = jj == 0 ? w[0] : w[(jj < 0 ? -jj : jj)];
+  }
+  // lattice constants
+  LatticeConst& L = c->L;
+  std::memset(&L, 0, sizeof(L));
+  for (int j = 0; j < Q1; ++j) {
+    L.e[j] = c->e1[j];
+    const double cj = r * c->e1[j];
+    double fact = 1.0;
+    for (int n = 0; n <= c->N; ++n) {
+      if (n > 0) fact *= n;
+      const double h = hermite_1d(n, cj);
+      L.He[j][n] = static_cast<float>(h);
+      L.Rw[j][n] = static_cast<float>(c->w1[j] * h / fact);
+    }
+  }
+  L.r = r;
+  for (int k = 0; k < 3; ++k) L.k[k] = desc->shift_k[k];
+  for (int n = 0; n <= kMaxN; ++n)
+    for (int m = 0; m < 3; ++m) L.tau[n][m] = (n <= c->N && 2 * m <= n) ? desc->tau[n][m] : 1.0;
+  L.tau[2][1] = 1.0;
+  L.rho_ref = desc->rho_ref;
+  L.tau_offset = desc->tau_offset_half ? 0.5 : 0.0;
+  L.density_scaling = desc->tau_density_scaling ? 1 : 0;
+
+  // domains, node space, block table
+  c->doms.assign(domains, domains + n_domains);
+  long long off = 0;
+  std::vector<DomainDev> dd(n_domains);
+  long long max_local = 0;
+  for (int i = 0; i < n_domains; ++i) {
+    const lbsmrt_domain& D = domains[i];
+    if (D.nx < 1 || D.ny < 1 || D.nz < 1 || (D.bc_x != 0 && D.bc_x != 1)) { free_ctx(c); return LBSMRT_E_ARG; }
+    const long long n = static_cast<long long>(D.nx) * D.ny * D.nz;
+    if (D.bc_x == 1) {
+      c->shock = true;
+      if (!(D.rho_in > 0 && D.rho_out > 0 && D.theta_in > 0 && D.theta_in < 2 && D.theta_out > 0 && D.theta_out < 2)) {
+        free_ctx(c);
+        return LBSMRT_E_ARG;
+      }
+    }
+    dd[i].off = off;
+    dd[i].nx = D.nx; dd[i].ny = D.ny; dd[i].nz = D.nz;
+    dd[i].bc_x = D.bc_x;
+    dd[i].ghost = 2 * i;
+    dd[i].pad = 0;
+    c->dom_off.push_back(off);
+    off += n;
+    if (n > max_local) max_local = n;
+  }
+  c->n_nodes = off;
+  if (off >= (1LL << 30)) { free_ctx(c); return LBSMRT_E_ARG; }   // 32-bit node offsets in the kernels
+  c->stride = (off + 63) / 64 * 64;
+  c->block = (max_local >= 4096) ? 256 : 64;
+  std::vector<BlockDev> bl;
+  for (int i = 0; i < n_domains; ++i) {
+    const long long n = static_cast<long long>(domains[i].nx) * domains[i].ny * domains[i].nz;
+    for (long long first = 0; first < n; first += c->block) bl.push_back(BlockDev{i, static_cast<int>(first)});
+  }
+  c->n_blocks = static_cast<int>(bl.size());
+  c->n_ghost = 2 * n_domains;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return LBSMRT_E_HIP; }
+  auto fail = [&](lbsmrt_status code) { free_ctx(c); return code; };
+  if (hipMalloc(&c->d_doms, sizeof(DomainDev) * dd.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_blocks, sizeof(BlockDev) * bl.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_ghost, sizeof(float) * c->Q * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_ghost_fields, sizeof(double) * 5 * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
+  std::vector<double> gf(5 * c->n_ghost, 0.0);
+  for (int i = 0; i < n_domains; ++i) {
+    const lbsmrt_domain& D = domains[i];
+    const bool sh = D.bc_x == 1;
+    const double rin = sh ? D.rho_in : 1.0, rout = sh ? D.rho_out : 1.0;
+    const double tin = sh ? D.theta_in : 1.0, tout = sh ? D.theta_out : 1.0;
+    for (int side = 0; side < 2; ++side) {
+      const int col = 2 * i + side;
+      gf[0 * c->n_ghost + col] = side ? rout : rin;
+      for (int k = 0; k < 3; ++k) gf[(1 + k) * c->n_ghost + col] = sh ? (side ? D.u_out[k] : D.u_in[k]) : r * L.k[k];
+      gf[4 * c->n_ghost + col] = side ? tout : tin;
+    }
+  }
+  if (hipMemcpyAsync(c->d_doms, dd.data(), sizeof(DomainDev) * dd.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->d_blocks, bl.data(), sizeof(BlockDev) * bl.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->d_ghost_fields, gf.data(), sizeof(double) * gf.size(), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemsetAsync(c->d_err, 0, sizeof(int), s) != hipSuccess)
+    return fail(LBSMRT_E_HIP);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::equilibrium(c, c->d_ghost_fields, c->n_ghost, c->d_ghost, c->n_ghost, s); });
+  if (hipGetLastError() != hipSuccess) return fail(LBSMRT_E_HIP);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(LBSMRT_E_HIP);
+  *out = c;
+  return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_get_info(const lbsmrt_ctx* c, lbsmrt_info* o) {
+  if (!c || !o) return LBSMRT_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->Q = c->Q; o->Q1 = c->Q1; o->M = c->M; o->N = c->N;
+  o->c_l = c->r;
+  for (int j = 0; j < c->Q1; ++j) { o->w1d[j] = c->w1[j]; o->e1d[j] = c->e1[j]; }
+  o->n_nodes = c->n_nodes;
+  o->f_stride = c->stride;
+  o->f_len = c->stride * c->Q;
+  o->n_domains = static_cast<int>(c->doms.size());
+  for (size_t i = 0; i < c->dom_off.size() && i < 64; ++i) o->domain_offset[i] = c->dom_off[i];
+  return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_step(lbsmrt_ctx* c, float* f_a, float* f_b, int n_steps, void* stream) {
+  if (!c || !f_a || !f_b || f_a == f_b || n_steps < 1) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const StepArgs A = step_args(c);
+  for (int t = 0; t < n_steps; ++t) {
+    const float* src = (t & 1) ? f_b : f_a;
+    float* dst = (t & 1) ? f_a : f_b;
+    dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::step(c, A, src, dst, s); });
+  }
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+int lbsmrt_moment_rows(const lbsmrt_ctx* c, unsigned mask) {
+  if (!c) return -1;
+  int rows = 0;
+  if (mask & LBSMRT_MOM_BASIC) rows += 5;
+  if (mask & LBSMRT_MOM_SIGMA) rows += 6;
+  if (mask & LBSMRT_MOM_Q) rows += 3;
+  if (mask & LBSMRT_MOM_M3) rows += 10;
+  if (c->N >= 4) {
+    if (mask & LBSMRT_MOM_R41) rows += 6;
+    if (mask & LBSMRT_MOM_R42) rows += 1;
+  }
+  if (mask & LBSMRT_MOM_DLOCAL) rows += c->M;
+  if (mask & LBSMRT_MOM_ALAB) rows += c->M;
+  return rows;
+}
+
+lbsmrt_status lbsmrt_moments(lbsmrt_ctx* c, const float* f, double* out, unsigned mask, void* stream) {
+  if (!c || !f || !out || mask == 0 || (mask & ~0xFFu)) return LBSMRT_E_ARG;
+  if (c->N < 4 && (mask & (LBSMRT_MOM_R41 | LBSMRT_MOM_R42))) return LBSMRT_E_ARG;
+  if (c->N < 3 && (mask & (LBSMRT_MOM_Q | LBSMRT_MOM_M3))) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const StepArgs A = step_args(c);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::moments(c, A, f, out, mask, s); });
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* c, const double* fields, float* f, void* stream) {
+  if (!c || !fields || !f) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::equilibrium(c, fields, c->n_nodes, f, c->stride, s); });
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* lam_next, float* lam_t,
+                                  double* dL_dtau, void* stream) {
+  (void)stream;
+  if (!c || !f_t || !lam_next || !lam_t || !dL_dtau || lam_t == lam_next) return LBSMRT_E_ARG;
+  return LBSMRT_E_UNSUPPORTED;
+}
+
+lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* c, const float* f, const double* target, const double* scales, float* lam,
+                               double* loss, void* stream) {
+  (void)stream;
+  if (!c || !f || !target || !scales || !lam || !loss) return LBSMRT_E_ARG;
+  return LBSMRT_E_UNSUPPORTED;
+}
+
+lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* c, void* stream) {
+  if (!c) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h != 0) {
+    HIP_TRY(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LBSMRT_E_STATE;
+  }
+  return LBSMRT_OK;
+}
+
+void lbsmrt_destroy(lbsmrt_ctx* c) { free_ctx(c); }
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+"""Python face of the LB-SMRT library: a lattice context over caller-owned
+torch device tensors.  PyTorch supplies device memory and the stream only."""
+import ctypes
+
+import torch
+
+from . import _lib as C
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One LB-SMRT configuration: velocity set, truncation order, relaxation
+    times and a list of domains (see include/lbsmrt.h for every field).
+
+    tau: dict {(n, m): tau_nm} in time-step units at rho_ref.
+    domains: list of dicts with nx, ny, nz, bc_x and, for bc_x = 1,
+    rho_in, u_in, theta_in, rho_out, u_out, theta_out (lab frame).
+    """
+
+    def __init__(self, abscissae, degree, N, tau, domains, shift_k=(0, 0, 0), rho_ref=1.0,
+                 tau_density_scaling=True, tau_offset_half=True, precision="fp32"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the LB-SMRT library runs on a gfx950 GPU; no GPU is visible")
+        lib = C.lib()
+        d = C.LatticeDesc()
+        d.n_abscissa = len(abscissae)
+        for i, a in enumerate(abscissae):
+            d.abscissa[i] = int(a)
+        d.degree = int(degree)
+        d.order_N = int(N)
+        for k in range(3):
+            d.shift_k[k] = int(shift_k[k])
+        for n in range(6):
+            for m in range(3):
+                d.tau[n][m] = float(tau.get((n, m), 1.0)) if (n >= 2 and 2 * m <= n) else 1.0
+        d.rho_ref = float(rho_ref)
+        d.tau_density_scaling = int(bool(tau_density_scaling))
+        d.tau_offset_half = int(bool(tau_offset_half))
+        d.regularized = 1
+        d.precision = {"fp32": C.FP32, "split_bf16x3": C.SPLIT_BF16X3}[precision]
+        arr = (C.DomainDesc * len(domains))()
+        for i, dom in enumerate(domains):
+            x = arr[i]
+            x.nx, x.ny, x.nz = int(dom["nx"]), int(dom.get("ny", 1)), int(dom.get("nz", 1))
+            x.bc_x = int(dom.get("bc_x", 0))
+            if x.bc_x == 1:
+                x.rho_in, x.theta_in = float(dom["rho_in"]), float(dom["theta_in"])
+                x.rho_out, x.theta_out = float(dom["rho_out"]), float(dom["theta_out"])
+                for k in range(3):
+                    x.u_in[k] = float(dom["u_in"][k])
+                    x.u_out[k] = float(dom["u_out"][k])
+        self.domains = [dict(dm) for dm in domains]
+        self.tau = dict(tau)
+        self.shift_k = tuple(int(v) for v in shift_k)
+        h = ctypes.c_void_p()
+        C.check(lib.lbsmrt_init_lattice(ctypes.byref(d), arr, len(domains), _stream_ptr(), ctypes.byref(h)),
+                "lbsmrt_init_lattice")
+        self._h = h
+        info = C.Info()
+        C.check(lib.lbsmrt_get_info(h, ctypes.byref(info)), "lbsmrt_get_info")
+        self.Q, self.Q1, self.M, self.N = info.Q, info.Q1, info.M, info.N
+        self.c_l = info.c_l
+        self.w1d = [info.w1d[i] for i in range(self.Q1)]
+        self.e1d = [info.e1d[i] for i in range(self.Q1)]
+        self.n_nodes = info.n_nodes
+        self.f_stride = info.f_stride
+        self.domain_offset = [info.domain_offset[i] for i in range(min(info.n_domains, 64))]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    # -- buffers ------------------------------------------------------------
+    def new_state(self):
+        return torch.empty((self.Q, self.f_stride), dtype=torch.float32, device=self.device)
+
+    # -- calls --------------------------------------------------------------
+    def equilibrium(self, fields, out=None):
+        """fields: float64 (5, n_nodes) rows rho, u_x, u_y, u_z, theta (lab frame)."""
+        f = self.new_state() if out is None else out
+        C.check(C.lib().lbsmrt_equilibrium(self._h, _dev_ptr(fields, torch.float64, "fields"),
+                                           _dev_ptr(f, torch.float32, "f"), _stream_ptr()), "lbsmrt_equilibrium")
+        return f
+
+    def step(self, f_a, f_b, n_steps=1):
+        """Advance n_steps; returns whichever of f_a, f_b holds the result."""
+        C.check(C.lib().lbsmrt_step(self._h, _dev_ptr(f_a, torch.float32, "f_a"), _dev_ptr(f_b, torch.float32, "f_b"),
+                                    int(n_steps), _stream_ptr()), "lbsmrt_step")
+        return f_a if n_steps % 2 == 0 else f_b
+
+    def moment_rows(self, mask):
+        return C.lib().lbsmrt_moment_rows(self._h, mask)
+
+    def moments(self, f, mask=C.MOM_BASIC, out=None):
+        rows = self.moment_rows(mask)
+        o = torch.empty((rows, self.n_nodes), dtype=torch.float64, device=self.device) if out is None else out
+        C.check(C.lib().lbsmrt_moments(self._h, _dev_ptr(f, torch.float32, "f"), _dev_ptr(o, torch.float64, "out"),
+                                       int(mask), _stream_ptr()), "lbsmrt_moments")
+        return o
+
+    def step_adjoint(self, f_t, lam_next, lam_t, dL_dtau):
+        C.check(C.lib().lbsmrt_step_adjoint(self._h, _dev_ptr(f_t, torch.float32, "f_t"),
+                                            _dev_ptr(lam_next, torch.float32, "lam_next"),
+                                            _dev_ptr(lam_t, torch.float32, "lam_t"),
+                                            _dev_ptr(dL_dtau, torch.float64, "dL_dtau"), _stream_ptr()),
+                "lbsmrt_step_adjoint")
+        return lam_t
+
+    def loss_seed(self, f, target, scales, lam, loss):
+        sc = (ctypes.c_double * 3)(*[float(s) for s in scales])
+        C.check(C.lib().lbsmrt_loss_seed(self._h, _dev_ptr(f, torch.float32, "f"),
+                                         _dev_ptr(target, torch.float64, "target"), sc,
+                                         _dev_ptr(lam, torch.float32, "lam"), _dev_ptr(loss, torch.float64, "loss"),
+                                         _stream_ptr()), "lbsmrt_loss_seed")
+        return lam
+
+    def sync(self):
+        """Wait for the current stream; raise if a node left the validity region."""
+        C.check(C.lib().lbsmrt_sync_status(self._h, _stream_ptr()), "lbsmrt_sync_status")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            C.lib().lbsmrt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,68 @@
+"""Shared set-up of the workloads for tests: the same physical configuration
+built once for the oracle and once for the HIP library, from the same seeded
+inputs (paper_2401_11086_amd.workloads)."""
+import math
+
+import numpy as np
+
+import oracle as O
+from paper_2401_11086_amd import workloads as W
+
+D1Q7 = ([1, 2, 3], 9)
+D1Q9 = ([1, 2, 3, 5], 11)
+
+# Table 3 temperatures where the paper prints them; otherwise theta2 = 1.07
+TABLE3_THETA1 = {1.5: 0.714, 3.0: 0.333, 5.0: 0.167, 7.0: 0.071}
+
+
+def shock_case(Ma, nx, stencil=D1Q7, N=4, table=None, width=5.0):
+    """Normal shock in a tube with fixed Maxwellian ends: RH states (oracle's
+    own function), k = nearest shift, tau_20 from cells of half an upstream mean
+    free path (l = tau sqrt(theta))."""
+    table = table or O.TAU_STAR_SMRT
+    ab, deg = stencil
+    vs = O.make_velocity_set(ab, deg)
+    if Ma in TABLE3_THETA1:
+        st = O.rankine_hugoniot(Ma, theta1=TABLE3_THETA1[Ma])
+    else:
+        st = O.rankine_hugoniot(Ma, theta2=1.07)
+    k = O.shift_integer(st["u_mid"], vs.r)
+    tau20 = 2.0 * vs.r / math.sqrt(st["theta1"])
+    tau = {key: float(v) * tau20 for key, v in table.items()}
+    model = O.Model(vs=vs, N=N, tau=tau, shift=(k, 0, 0), rho_ref=1.0)
+    dom_o = O.Domain(nx=nx, bc_x=1, state_in=(1.0, (st["u1"], 0.0, 0.0), st["theta1"]),
+                     state_out=(st["rho2"], (st["u2"], 0.0, 0.0), st["theta2"]))
+    dom_g = dict(nx=nx, ny=1, nz=1, bc_x=1, rho_in=1.0, u_in=(st["u1"], 0.0, 0.0), theta_in=st["theta1"],
+                 rho_out=st["rho2"], u_out=(st["u2"], 0.0, 0.0), theta_out=st["theta2"])
+    fields = W.tanh_profile(nx, (1.0, st["u1"], st["theta1"]), (st["rho2"], st["u2"], st["theta2"]), width)
+    lat_kw = dict(abscissae=ab, degree=deg, N=N, tau=tau, domains=[dom_g], shift_k=(k, 0, 0), rho_ref=1.0)
+    return dict(model=model, dom=dom_o, fields=fields, lat_kw=lat_kw, states=st, nx=nx, ny=1, nz=1)
+
+
+def box_case(n, stencil=D1Q7, N=4, Kn=0.05, seed=0, table=None, n_ref=None):
+    """Periodic box with a Fourier-mode perturbed Maxwellian (rho0 = theta0 = 1).
+    Kn = l0 / L with l0 = tau20 sqrt(theta0) and L = n_ref cells of size c_l."""
+    table = table or O.TAU_STAR_SMRT
+    ab, deg = stencil
+    vs = O.make_velocity_set(ab, deg)
+    tau20 = Kn * (n_ref or n) * vs.r
+    tau = {key: float(v) * tau20 for key, v in table.items()}
+    model = O.Model(vs=vs, N=N, tau=tau, shift=(0, 0, 0), rho_ref=1.0)
+    dom_o = O.Domain(nx=n, ny=n, nz=n, bc_x=0)
+    dom_g = dict(nx=n, ny=n, nz=n, bc_x=0)
+    fields = W.fourier_box(n, seed=seed)
+    lat_kw = dict(abscissae=ab, degree=deg, N=N, tau=tau, domains=[dom_g], shift_k=(0, 0, 0), rho_ref=1.0)
+    return dict(model=model, dom=dom_o, fields=fields, lat_kw=lat_kw, nx=n, ny=n, nz=n)
+
+
+def oracle_state_from_gpu(f_gpu_np, case):
+    """[Q][stride] float32 (host copy) -> oracle layout (Q, nz, ny, nx) float64."""
+    n = case["nx"] * case["ny"] * case["nz"]
+    return f_gpu_np[:, :n].astype(np.float64).reshape(-1, case["nz"], case["ny"], case["nx"])
+
+
+def family_error(x_gpu, x_ref, order, rho_ref=1.0, theta_ref=1.0):
+    """Scale-relative error of a moment family of Hermite order n:
+    max|x_gpu - x_ref| / max(max|x_ref|, rho_ref theta_ref^(n/2))."""
+    scale = max(float(np.abs(x_ref).max()), rho_ref * theta_ref ** (order / 2.0))
+    return float(np.abs(np.asarray(x_gpu) - np.asarray(x_ref)).max()) / scale

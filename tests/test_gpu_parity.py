@@ -1,0 +1,221 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs.  Tolerances: one step from an identical FP32 state, every
+moment family within 1e-5 of its scale (max|ref| or rho_ref theta_ref^(n/2));
+multi-step trajectories within 1e-4 on normalised profiles."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_11086_amd import workloads as W
+
+from cases import D1Q7, D1Q9, box_case, family_error, oracle_state_from_gpu, shock_case
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-5
+TOL_PROFILE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _lattice(case):
+    from paper_2401_11086_amd import Lattice
+    return Lattice(**case["lat_kw"])
+
+
+def _gpu_state(torch, lat, case, noise_seed=None, amp=0.02):
+    fields = torch.tensor(case["fields"], dtype=torch.float64, device="cuda")
+    f = lat.equilibrium(fields)
+    if noise_seed is not None:
+        n = case["nx"] * case["ny"] * case["nz"]
+        noise = torch.tensor(W.state_noise((lat.Q, n), seed=noise_seed, amp=amp), dtype=torch.float32, device="cuda")
+        f[:, :n] *= noise
+    torch.cuda.synchronize()
+    return f
+
+
+def _host(f):
+    return f.detach().cpu().numpy()
+
+
+def _gpu_moments(lat, f, mask):
+    return lat.moments(f, mask).cpu().numpy()
+
+
+def _compare_observables(lat, f_gpu, f_oracle, case, tol):
+    from paper_2401_11086_amd import _lib as C
+    mask = C.MOM_BASIC | C.MOM_SIGMA | C.MOM_Q | C.MOM_M3 | C.MOM_DLOCAL | C.MOM_ALAB
+    if case["model"].N >= 4:
+        mask |= C.MOM_R41 | C.MOM_R42
+    g = _gpu_moments(lat, f_gpu, mask)
+    ob = O.observables(f_oracle, case["model"], case["dom"])
+    M = case["model"].M
+    rows = {}
+    r = 0
+    for name, cnt in [("basic", 5), ("sigma", 6), ("q", 3), ("m", 10), ("R41", 6), ("R42", 1), ("d", M), ("a", M)]:
+        if name in ("R41", "R42") and case["model"].N < 4:
+            continue
+        rows[name] = g[r:r + cnt]
+        r += cnt
+    errs = {
+        "rho": family_error(rows["basic"][0], ob["rho"], 0),
+        "u": family_error(rows["basic"][1:4], ob["u"], 1),
+        "theta": family_error(rows["basic"][4], ob["theta"], 2),
+        "sigma": family_error(rows["sigma"], ob["sigma"], 2),
+        "q": family_error(rows["q"], ob["q"], 3),
+        "m": family_error(rows["m"], ob["m"], 3),
+    }
+    if case["model"].N >= 4:
+        errs["R41"] = family_error(rows["R41"], ob["R41"], 4)
+        errs["R42"] = family_error(rows["R42"], ob["R42"], 4)
+    sl = 0
+    for n in range(case["model"].N + 1):
+        cnt = (n + 1) * (n + 2) // 2
+        errs[f"d{n}"] = family_error(rows["d"][sl:sl + cnt], ob["d"][sl:sl + cnt], n)
+        sl += cnt
+    a_ref = O.project(O.stream(f_oracle, case["model"], case["dom"]).reshape(case["model"].vs.Q, -1), case["model"])
+    sl = 0
+    for n in range(case["model"].N + 1):
+        cnt = (n + 1) * (n + 2) // 2
+        errs[f"a{n}"] = family_error(rows["a"][sl:sl + cnt], a_ref[sl:sl + cnt], n)
+        sl += cnt
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"moment families over {tol}: {bad} (all: {errs})"
+    return errs
+
+
+CASES = {
+    "shock_q343_n4_ma1.2": lambda: shock_case(1.2, 200, D1Q7, 4),
+    "shock_q729_n5_ma3": lambda: shock_case(3.0, 120, D1Q9, 5),
+    "shock_q729_n4_ma1.5": lambda: shock_case(1.5, 64, D1Q9, 4),
+    "box_q343_n4_12": lambda: box_case(12, D1Q7, 4, n_ref=32),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_equilibrium_fill_matches_oracle(torch, name):
+    case = CASES[name]()
+    lat = _lattice(case)
+    f = _host(_gpu_state(torch, lat, case))
+    fo = O.equilibrium_f(case["fields"][0], case["fields"][1:4], case["fields"][4], case["model"])
+    n = case["nx"] * case["ny"] * case["nz"]
+    err = np.abs(f[:, :n] - fo).max() / np.abs(fo).max()
+    assert err < 1e-6, err
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_step_matches_oracle(torch, name):
+    case = CASES[name]()
+    lat = _lattice(case)
+    f0 = _gpu_state(torch, lat, case, noise_seed=1)
+    fo0 = oracle_state_from_gpu(_host(f0), case)
+    _compare_observables(lat, f0, fo0, case, TOL_STEP)
+    f1 = lat.new_state()
+    out = lat.step(f0, f1, 1)
+    lat.sync()
+    fo1 = O.step(fo0, case["model"], case["dom"])
+    n = case["nx"] * case["ny"] * case["nz"]
+    g = _host(out)[:, :n].reshape(fo1.shape)
+    assert np.abs(g - fo1).max() / np.abs(fo1).max() < TOL_STEP
+    _compare_observables(lat, out, fo1, case, TOL_STEP)
+
+
+def _normalised(ob_rho, ob_th, ob_q, st):
+    return ((ob_rho - st["rho1"]) / (st["rho2"] - st["rho1"]),
+            (ob_th - st["theta1"]) / (st["theta2"] - st["theta1"]),
+            ob_q / (st["rho1"] * st["theta1"] ** 1.5))
+
+
+def _crossing(rho_hat):
+    """Fractional cell index where the normalised density crosses 1/2."""
+    i = int(np.argmax(rho_hat >= 0.5))
+    return i - 1 + (0.5 - rho_hat[i - 1]) / (rho_hat[i] - rho_hat[i - 1])
+
+
+def _shift_profile(y, dx):
+    """y(x + dx) by linear interpolation (ends held)."""
+    x = np.arange(len(y), dtype=float)
+    return np.interp(x + dx, x, y)
+
+
+def test_shock_trajectory_1000_steps_matches_oracle(torch):
+    """Ma = 1.2, D3Q343, N = 4, Nx = 200: normalised rho, theta, q_x every 100 steps.
+    A shock between two fixed Maxwellian ends is translation-neutral: FP32
+    round-off in the mass balance moves it without a restoring force, so the
+    profiles are compared after aligning the rho_hat = 1/2 crossing; the raw
+    (unaligned) difference and the drift are reported."""
+    from paper_2401_11086_amd import _lib as C
+    case = shock_case(1.2, 200, D1Q7, 4)
+    lat = _lattice(case)
+    fa = _gpu_state(torch, lat, case)
+    fb = lat.new_state()
+    fo = oracle_state_from_gpu(_host(fa), case)
+    st = case["states"]
+    worst = 0.0
+    for seg in range(10):
+        cur = lat.step(fa, fb, 100)
+        if cur is fb:
+            fa, fb = fb, fa
+        lat.sync()
+        for _ in range(100):
+            fo = O.step(fo, case["model"], case["dom"])
+        g = _gpu_moments(lat, fa, C.MOM_BASIC | C.MOM_Q)
+        ob = O.observables(fo, case["model"], case["dom"])
+        gn = _normalised(g[0], g[4], g[5], st)
+        on = _normalised(ob["rho"], ob["theta"], ob["q"][0], st)
+        raw = max(float(np.abs(a - b).max()) for a, b in zip(gn, on))
+        dx = _crossing(gn[0]) - _crossing(on[0])
+        e = max(float(np.abs(_shift_profile(a, dx) - b)[5:-5].max()) for a, b in zip(gn, on))
+        print(f"step {100 * (seg + 1)}: raw {raw:.2e}, shock offset {dx:+.2e} cells, aligned {e:.2e}, "
+              f"mass gpu-oracle {float(g[0].sum() - ob['rho'].sum()):+.2e}")
+        worst = max(worst, e)
+        assert e < TOL_PROFILE, (seg, e)
+        assert raw < 10 * TOL_PROFILE, (seg, raw)
+    print(f"worst aligned normalised-profile error over 1000 steps: {worst:.3e}")
+
+
+def test_box_trajectory_matches_oracle(torch):
+    """12^3 periodic Fourier box, 20 steps: every moment family within 1e-4."""
+    case = box_case(12, D1Q7, 4, n_ref=32)
+    lat = _lattice(case)
+    fa = _gpu_state(torch, lat, case)
+    fb = lat.new_state()
+    fo = oracle_state_from_gpu(_host(fa), case)
+    cur = lat.step(fa, fb, 20)
+    lat.sync()
+    for _ in range(20):
+        fo = O.step(fo, case["model"], case["dom"])
+    _compare_observables(lat, cur, fo, case, TOL_PROFILE)
+
+
+def test_invalid_state_is_reported(torch):
+    from paper_2401_11086_amd import LbsmrtError
+    from paper_2401_11086_amd import _lib as C
+    case = shock_case(1.2, 64, D1Q7, 4)
+    case["fields"][4, 10:40] = 2.3   # theta above the Hermite convergence bound, wider than the stencil
+    lat = _lattice(case)
+    fa = _gpu_state(torch, lat, case)
+    fb = lat.new_state()
+    lat.step(fa, fb, 1)
+    with pytest.raises(LbsmrtError) as e:
+        lat.sync()
+    assert e.value.status == C.E_STATE
+    lat.sync()   # the flag was cleared by the read
+
+
+def test_step_is_bitwise_deterministic(torch):
+    case = box_case(10, D1Q7, 4)
+    lat = _lattice(case)
+    f0 = _gpu_state(torch, lat, case, noise_seed=3)
+    a, b = lat.new_state(), lat.new_state()
+    lat.step(f0, a, 1)
+    lat.step(f0, b, 1)
+    lat.sync()
+    n = lat.n_nodes
+    assert torch.equal(a[:, :n], b[:, :n])
