@@ -66,6 +66,26 @@ def cpu_baseline(ab, deg, N, edge, kn, sample_edge=32, steps=12):
                       f"{dt:.1f} s; numpy FP64 with {threads} BLAS threads"}
 
 
+def copy_calibration(torch, n_floats, steps, warmup):
+    """Plain device-to-device copy of an f-sized float32 buffer: the achievable
+    HBM rate for a read + write stream, and the reference for the traffic counters."""
+    a = torch.ones(n_floats, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(max(warmup, 1)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    gbs = 2.0 * 4 * n_floats / (ms / 1e3) / 1e9
+    print(json.dumps({"metric": "device copy GB/s (read + write)", "value": round(gbs, 1), "unit": "GB/s",
+                      "bytes_per_launch": 8 * n_floats, "ms_per_copy": round(ms, 4), "steps": steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +93,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="box256_q343_n4", choices=sorted(WORKLOADS))
     ap.add_argument("--kn", type=float, default=0.05)
+    ap.add_argument("--precision", default="fp64_contract", choices=["fp32", "fp64_contract"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="time a plain device copy of one f buffer instead (HBM calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -87,11 +110,14 @@ def main():
 
     ab, deg, N, edge = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    _progress(f"workload {args.workload}: building lattice")
+    if args.calibrate_copy:
+        copy_calibration(torch, 343 * edge ** 3 if N == 4 else 729 * edge ** 3, args.steps, args.warmup)
+        return
+    _progress(f"workload {args.workload} ({args.precision}): building lattice")
     r_guess = {9: 1.19697977039307, 11: 0.678003906334339}[deg]
     tau20 = args.kn * edge * r_guess
     tau = {k: v * tau20 for k, v in TAU_STAR.items() if k[0] <= N}
-    lat = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)])
+    lat = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision=args.precision)
     assert abs(lat.c_l - r_guess) < 1e-12
     fields = W.fourier_box_torch(edge, "cuda")
     fa = lat.equilibrium(fields)
@@ -138,8 +164,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{edge}^3 periodic box, D3Q{lat.Q} (D1Q{lat.Q1} degree {deg}), Hermite N={N}, "
-                               f"Kn={args.kn}, 16 Fourier modes per field, FP32 state + FP64 moment section",
-                   "nodes": nodes, "Q": lat.Q, "M": lat.M, "precision": "fp32"},
+                               f"Kn={args.kn}, 16 Fourier modes per field, FP32 state, "
+                               + ("FP64 folded contractions" if args.precision == "fp64_contract"
+                                  else "FP32 contractions") + ", FP64 moment section",
+                   "nodes": nodes, "Q": lat.Q, "M": lat.M, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": f"k_collide_stream<{lat.Q1},{N}>", "bytes_per_launch": bytes_per_launch},

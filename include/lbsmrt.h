@@ -52,7 +52,12 @@ typedef enum {
   LBSMRT_E_UNSUPPORTED = 6   /* a (Q1, N) pair with no compiled kernel */
 } lbsmrt_status;
 
-typedef enum { LBSMRT_FP32 = 0, LBSMRT_SPLIT_BF16X3 = 1 } lbsmrt_precision;
+/* Arithmetic of the projection / rebuild contractions.  The state f is float32 in every mode.
+ *  LBSMRT_FP32          FP32 contractions; conserved sums, frame shift and relaxation in FP64.
+ *  LBSMRT_SPLIT_BF16X3  reserved (returns LBSMRT_E_UNSUPPORTED).
+ *  LBSMRT_FP64_CONTRACT FP64 contractions folded over +-e pairs: the rebuild then conserves
+ *                       mass, momentum and energy up to the float32 rounding of the stored f. */
+typedef enum { LBSMRT_FP32 = 0, LBSMRT_SPLIT_BF16X3 = 1, LBSMRT_FP64_CONTRACT = 2 } lbsmrt_precision;
 
 /* Velocity set and collision model (Sec. 4.2, Tables 3 and 4). */
 typedef struct {
@@ -153,6 +158,11 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* ctx, const float* f_t, const float
  * and L into *loss (float64, device).  Asynchronous. */
 lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* ctx, const float* f, const double* target,
                                const double* scales, float* lam, double* loss, void* stream);
+
+/* Replace the relaxation times: tau[n*3 + m] = tau_nm at rho_ref for n = 2..N (the (2,1)
+ * entry is ignored), as in lbsmrt_lattice_desc.tau.  Host-side; takes effect for work
+ * enqueued afterwards.  E_ARG if an entry is not positive and finite. */
+lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* ctx, const double* tau);
 
 /* Wait for `stream` and report (and clear) the latched device state flag. */
 lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* ctx, void* stream);

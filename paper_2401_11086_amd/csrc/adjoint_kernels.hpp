@@ -1,0 +1,229 @@
+// Adjoint step, loss seed and the deterministic reduction of per-block partials.
+#pragma once
+#include "adjoint.hpp"
+
+namespace lbsmrt {
+
+constexpr int kTauCols = (kMaxN + 1) * 3;   // dL/dtau[n][m] flattened as n*3+m
+
+// Scatter of mu = P^T abar to the streaming sources: out[q][x - s_q] = sum_alpha He_alpha(c_q) abar_alpha.
+// Populations whose source was a ghost cell (shock ends) are skipped.
+template <int Q1, int N, bool SHOCK>
+__device__ __forceinline__ void scatter_transpose_projection(const LatticeConst& L, const Pull<Q1>& P,
+                                                             const double (&ab)[n_moments(N)],
+                                                             float* __restrict__ out, long long stride) {
+  constexpr int p = Q1 / 2;
+  constexpr int P2 = n_sym(N);
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    const int xs = source_x<Q1>(L, P, ix);
+    if (SHOCK && xs < 0) continue;
+    const unsigned xoff = static_cast<unsigned>(P.row + xs) * 4u;
+    double hx[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) hx[n] = L.He64[ix][n];
+    double u2[P2];
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        if (ay + az > N) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int ax = 0; ax <= N; ++ax)
+          if (ax + ay + az <= N) s = fma(ab[midx(ax, ay, az)], hx[ax], s);
+        u2[pair_pos(ay, az)] = s;
+      }
+    float* __restrict__ slab = out + static_cast<size_t>(ix * Q1 * Q1) * stride;
+    auto zline = [&](int iy, const double (&v)[N + 1]) {
+      float* __restrict__ line = slab + static_cast<size_t>(iy * Q1) * stride;
+      const unsigned yoff = xoff + P.yo[iy];
+      {
+        double s = 0.0;
+#pragma unroll
+        for (int az = 0; az <= N; az += 2) s = fma(v[az], hermite_at_zero(az), s);
+        store_at(line + static_cast<size_t>(p) * stride, yoff + P.zo[p], static_cast<float>(s));
+      }
+#pragma unroll
+      for (int j = 1; j <= p; ++j) {
+        double e = 0.0, o = 0.0;
+#pragma unroll
+        for (int az = 0; az <= N; ++az) {
+          if (az & 1) o = fma(v[az], L.He64[p + j][az], o);
+          else e = fma(v[az], L.He64[p + j][az], e);
+        }
+        store_at(line + static_cast<size_t>(p + j) * stride, yoff + P.zo[p + j], static_cast<float>(e + o));
+        store_at(line + static_cast<size_t>(p - j) * stride, yoff + P.zo[p - j], static_cast<float>(e - o));
+      }
+    };
+    {
+      double v[N + 1];
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        double s = 0.0;
+#pragma unroll
+        for (int ay = 0; ay <= N; ay += 2)
+          if (ay + az <= N) s = fma(u2[pair_pos(ay, az)], hermite_at_zero(ay), s);
+        v[az] = s;
+      }
+      zline(p, v);
+    }
+#pragma unroll
+    for (int j = 1; j <= p; ++j) {
+      double vp[N + 1], vm[N + 1];
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        double e = 0.0, o = 0.0;
+#pragma unroll
+        for (int ay = 0; ay <= N; ++ay) {
+          if (ay + az > N) continue;
+          if (ay & 1) o = fma(u2[pair_pos(ay, az)], L.He64[p + j][ay], o);
+          else e = fma(u2[pair_pos(ay, az)], L.He64[p + j][ay], e);
+        }
+        vp[az] = e + o;
+        vm[az] = e - o;
+      }
+      zline(p + j, vp);
+      zline(p - j, vm);
+    }
+  }
+}
+
+// Shock tubes: populations of node x that stream out through an end of the domain
+// influence nothing; their adjoint is zero.
+template <int Q1>
+__device__ __forceinline__ void zero_outflow(const LatticeConst& L, const Pull<Q1>& P, float* __restrict__ out,
+                                             long long stride) {
+  const unsigned off = static_cast<unsigned>(P.node) * 4u;
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    const int xd = P.x + L.e[ix] + L.k[0];
+    if (xd >= 0 && xd < P.nx) continue;
+    float* __restrict__ slab = out + static_cast<size_t>(ix * Q1 * Q1) * stride;
+#pragma unroll
+    for (int qs = 0; qs < Q1 * Q1; ++qs) store_at(slab + static_cast<size_t>(qs) * stride, off, 0.0f);
+  }
+}
+
+// Fixed-order tree reduction of one value per thread; thread 0 receives the block sum.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// One adjoint step: lam_t = (d f_{t+1} / d f_t)^T lam_next, per-block partials of dL/dtau.
+template <int Q1, int N, bool SHOCK>
+__global__ __launch_bounds__(256) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
+                                                 const float* __restrict__ lam_next, float* __restrict__ lam_t,
+                                                 double* __restrict__ partial) {
+  constexpr int M = n_moments(N);
+  __shared__ double red[256];
+  Pull<Q1> P;
+  const bool active = make_pull<Q1>(L, A, P);
+  double tb[kMaxN + 1][3];
+#pragma unroll
+  for (int n = 0; n <= kMaxN; ++n)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) tb[n][m] = 0.0;
+  if (active) {
+    double d[M];
+    double S[5];
+    gather_project64<Q1, N, SHOCK>(L, A, f_t, P, d);
+    sums_from_a<N>(d, L, S);
+    const Macro mac = macro_from_sums(L, S, A.err);
+    to_local<N>(d, mac);
+    double ab[M];
+    own_project64<Q1, N, true>(L, lam_next, A.stride, P.node, ab);
+    node_adjoint<N>(L, mac, d, ab, tb);
+    scatter_transpose_projection<Q1, N, SHOCK>(L, P, ab, lam_t, A.stride);
+    if (SHOCK && P.bc_x == 1) zero_outflow<Q1>(L, P, lam_t, A.stride);
+  }
+#pragma unroll
+  for (int n = 0; n <= kMaxN; ++n)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const bool used = n >= 2 && n <= N && 2 * m <= n && !(n == 2 && m == 1);
+      const double s = used ? block_sum(tb[n][m], red) : 0.0;
+      if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * kTauCols + n * 3 + m] = s;
+    }
+}
+
+// Seed of the adjoint for L = sum_x [s0^2 (rho - rho*)^2 + s1^2 (theta - theta*)^2 + s2^2 (q_x - q_x*)^2]
+// on the pre-collision moments of state f.  lam[i][x - s_i] = dL/dg_i(x); per-block partial of L.
+template <int Q1, int N, bool SHOCK>
+__global__ __launch_bounds__(256) void k_loss_seed(LatticeConst L, StepArgs A, const float* __restrict__ f,
+                                                   const double* __restrict__ target, long long n_nodes, double s0,
+                                                   double s1, double s2, float* __restrict__ lam,
+                                                   double* __restrict__ partial) {
+  constexpr int M = n_moments(N);
+  constexpr int p = Q1 / 2;
+  __shared__ double red[256];
+  Pull<Q1> P;
+  const bool active = make_pull<Q1>(L, A, P);
+  double ell = 0.0;
+  if (active) {
+    double d[M];
+    double S[5];
+    gather_project64<Q1, N, SHOCK>(L, A, f, P, d);
+    sums_from_a<N>(d, L, S);
+    const Macro mac = macro_from_sums(L, S, A.err);
+    to_local<N>(d, mac);
+    const double rho = mac.rho, th = mac.th;
+    const double u[3] = {mac.ux, mac.uy, mac.uz};
+    double t3[3];
+    sym_trace<1>(d + order_start(3), t3);
+    const double qx = 0.5 * th * sqrt(th) * t3[0];
+    // pressure tensor P = theta (d2 + rho delta), row x: (xx, xy, xz)
+    const double Pxx = th * (d[midx(2, 0, 0)] + rho), Pxy = th * d[midx(1, 1, 0)], Pxz = th * d[midx(1, 0, 1)];
+    const double er = rho - target[P.node], et = th - target[n_nodes + P.node], eq = qx - target[2 * n_nodes + P.node];
+    ell = s0 * s0 * er * er + s1 * s1 * et * et + s2 * s2 * eq * eq;
+    const double cr = 2.0 * s0 * s0 * er, ct = 2.0 * s1 * s1 * et, cq = 2.0 * s2 * s2 * eq;
+    const double ir = 1.0 / rho;
+    const double kx = 1.5 * rho * th + Pxx;
+#pragma unroll 1
+    for (int ix = 0; ix < Q1; ++ix) {
+      const int xs = source_x<Q1>(L, P, ix);
+      if (SHOCK && xs < 0) continue;
+      const unsigned xoff = static_cast<unsigned>(P.row + xs) * 4u;
+      const double cx = L.r * L.e[ix] - u[0];
+#pragma unroll
+      for (int iy = 0; iy < Q1; ++iy) {
+        const double cy = L.r * L.e[iy] - u[1];
+#pragma unroll
+        for (int iz = 0; iz < Q1; ++iz) {
+          const double cz = L.r * L.e[iz] - u[2];
+          const double c2 = cx * cx + cy * cy + cz * cz;
+          const double dth = (c2 * (1.0 / 3.0) - th) * ir;
+          const double dq = 0.5 * cx * c2 - (kx * cx + Pxy * cy + Pxz * cz) * ir;
+          const double G = cr + ct * dth + cq * dq;
+          const int q = (ix * Q1 + iy) * Q1 + iz;
+          store_at(lam + static_cast<size_t>(q) * A.stride, xoff + P.yo[iy] + P.zo[iz], static_cast<float>(G));
+        }
+      }
+    }
+    if (SHOCK && P.bc_x == 1) zero_outflow<Q1>(L, P, lam, A.stride);
+    (void)p;
+  }
+  const double s = block_sum(ell, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[c] (+)= sum_b partial[b * cols + c] in block order (deterministic).
+__global__ void k_reduce_partials(const double* __restrict__ partial, int n_blocks, int cols, double* __restrict__ out,
+                                  int accumulate) {
+  const int c = threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int b = 0; b < n_blocks; ++b) s += partial[static_cast<size_t>(b) * cols + c];
+  out[c] = accumulate ? out[c] + s : s;
+}
+
+}  // namespace lbsmrt

@@ -190,6 +190,245 @@ __device__ __forceinline__ void gather_project(const LatticeConst& L, const Step
   }
 }
 
+// ---------------------------------------------------------------- FP64 folded contractions
+// The 1D stencil is symmetric (e_{p+j} = -e_{p-j}) and He_n has the parity of n,
+// so sums over a +-e pair split into an even part (sum of the pair) and an odd
+// part (difference): every 1D contraction over Q1 = 2p+1 points costs p+1
+// multiply-adds per output instead of Q1.
+
+// 1D table of a contraction: He_n(c_j) (RW = false) or w_j He_n(c_j) / n! (RW = true).
+template <bool RW>
+__device__ __forceinline__ double tab(const LatticeConst& L, int j, int n) {
+  return RW ? L.Rw64[j][n] : L.He64[j][n];
+}
+template <bool RW>
+__device__ __forceinline__ double tab_center(const LatticeConst& L, int p, int n) {
+  return (n & 1) ? 0.0 : (RW ? L.Rw64[p][n] : hermite_at_zero(n));
+}
+
+// One z line of a slab: t1[n] = sum_iz T_n(c_iz) g[iz], FP64.
+template <int Q1, int N, bool RW = false>
+__device__ __forceinline__ void fold_line_project(const LatticeConst& L, const float* g, double (&t1)[N + 1]) {
+  constexpr int p = Q1 / 2;
+  double P[p], Mn[p];
+#pragma unroll
+  for (int j = 1; j <= p; ++j) {
+    const double gp = static_cast<double>(g[p + j]);
+    const double gm = static_cast<double>(g[p - j]);
+    P[j - 1] = gp + gm;
+    Mn[j - 1] = gp - gm;
+  }
+  const double g0 = static_cast<double>(g[p]);
+#pragma unroll
+  for (int n = 0; n <= N; ++n) {
+    double s = (n & 1) ? 0.0 : tab_center<RW>(L, p, n) * g0;
+#pragma unroll
+    for (int j = 1; j <= p; ++j) s = fma(tab<RW>(L, p + j, n), (n & 1) ? Mn[j - 1] : P[j - 1], s);
+    t1[n] = s;
+  }
+}
+
+// One slab (fixed ix): t2[ay,az] = sum_{iy,iz} T_ay(c_iy) T_az(c_iz) g[iy][iz], FP64, folded in y and z.
+template <int Q1, int N, bool RW = false>
+__device__ __forceinline__ void fold_slab_project(const LatticeConst& L, const float (&gs)[Q1 * Q1],
+                                                  double (&t2)[n_sym(N)]) {
+  constexpr int p = Q1 / 2;
+  {
+    double tc[N + 1];
+    fold_line_project<Q1, N, RW>(L, gs + p * Q1, tc);
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az)
+        if (ay + az <= N) t2[pair_pos(ay, az)] = (ay & 1) ? 0.0 : tab_center<RW>(L, p, ay) * tc[az];
+  }
+#pragma unroll
+  for (int j = 1; j <= p; ++j) {
+    double tp[N + 1], tm[N + 1];
+    fold_line_project<Q1, N, RW>(L, gs + (p + j) * Q1, tp);
+    fold_line_project<Q1, N, RW>(L, gs + (p - j) * Q1, tm);
+#pragma unroll
+    for (int az = 0; az <= N; ++az) {
+      const double Pz = tp[az] + tm[az];
+      const double Mz = tp[az] - tm[az];
+#pragma unroll
+      for (int ay = 0; ay <= N; ++ay)
+        if (ay + az <= N) t2[pair_pos(ay, az)] = fma(tab<RW>(L, p + j, ay), (ay & 1) ? Mz : Pz, t2[pair_pos(ay, az)]);
+    }
+  }
+}
+
+// FP64 projection of a node's own populations (no streaming) with table T:
+//   out[ax,ay,az] = sum_{ix,iy,iz} T_ax(c_ix) T_ay(c_iy) T_az(c_iz) v[q]
+template <int Q1, int N, bool RW>
+__device__ __forceinline__ void own_project64(const LatticeConst& L, const float* __restrict__ v, long long stride,
+                                              int node, double (&out)[n_moments(N)]) {
+  constexpr int P2 = n_sym(N);
+  const unsigned off = static_cast<unsigned>(node) * 4u;
+#pragma unroll
+  for (int i = 0; i < n_moments(N); ++i) out[i] = 0.0;
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    const float* __restrict__ vx = v + static_cast<size_t>(ix * Q1 * Q1) * stride;
+    float gs[Q1 * Q1];
+#pragma unroll
+    for (int qs = 0; qs < Q1 * Q1; ++qs) gs[qs] = load_at(vx + static_cast<size_t>(qs) * stride, off);
+    double t2[P2];
+    fold_slab_project<Q1, N, RW>(L, gs, t2);
+    double hx[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) hx[n] = tab<RW>(L, ix, n);
+#pragma unroll
+    for (int ax = 0; ax <= N; ++ax)
+#pragma unroll
+      for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+        for (int az = 0; az <= N; ++az)
+          if (ax + ay + az <= N) out[midx(ax, ay, az)] = fma(t2[pair_pos(ay, az)], hx[ax], out[midx(ax, ay, az)]);
+  }
+}
+
+// Gather + FP64 projection (eq:an): a[ax,ay,az] = sum_ix He_ax(c_ix) t2_ix[ay,az].
+// rho = a_0, j = a_1 and sum g |c|^2 = sum_k a_{2 e_k} + 3 rho come out exactly in FP64.
+template <int Q1, int N, bool SHOCK>
+__device__ __forceinline__ void gather_project64(const LatticeConst& L, const StepArgs& A,
+                                                 const float* __restrict__ f, const Pull<Q1>& P,
+                                                 double (&a)[Shape<Q1, N>::M]) {
+  constexpr int P2 = Shape<Q1, N>::P2;
+#pragma unroll
+  for (int i = 0; i < Shape<Q1, N>::M; ++i) a[i] = 0.0;
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    const int xs = source_x<Q1>(L, P, ix);
+    const float* __restrict__ fx = f + static_cast<size_t>(ix * Q1 * Q1) * A.stride;
+    const unsigned xoff = static_cast<unsigned>(P.row + xs) * 4u;
+    float gs[Q1 * Q1];
+#pragma unroll
+    for (int iy = 0; iy < Q1; ++iy) {
+      const unsigned xyoff = xoff + P.yo[iy];
+#pragma unroll
+      for (int iz = 0; iz < Q1; ++iz) {
+        const int qs = iy * Q1 + iz;
+        if constexpr (SHOCK) {
+          if (xs >= 0) {
+            gs[qs] = load_at(fx + static_cast<size_t>(qs) * A.stride, xyoff + P.zo[iz]);
+          } else {
+            gs[qs] = A.ghosts[static_cast<size_t>(ix * Q1 * Q1 + qs) * A.n_ghost + P.gcol + (xs == -1 ? 0 : 1)];
+          }
+        } else {
+          gs[qs] = load_at(fx + static_cast<size_t>(qs) * A.stride, xyoff + P.zo[iz]);
+        }
+      }
+    }
+    double t2[P2];
+    fold_slab_project<Q1, N>(L, gs, t2);
+    double hx[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) hx[n] = L.He64[ix][n];
+#pragma unroll
+    for (int ax = 0; ax <= N; ++ax)
+#pragma unroll
+      for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+        for (int az = 0; az <= N; ++az)
+          if (ax + ay + az <= N) a[midx(ax, ay, az)] = fma(t2[pair_pos(ay, az)], hx[ax], a[midx(ax, ay, az)]);
+  }
+}
+
+// One z line of the rebuild: f[iz] = sum_az Rw_az(iz) v[az], stored as FP32.
+template <int Q1, int N>
+__device__ __forceinline__ void fold_line_store(const LatticeConst& L, const double (&v)[N + 1],
+                                                float* __restrict__ line_base, long long stride, unsigned off) {
+  constexpr int p = Q1 / 2;
+  {
+    double s = 0.0;
+#pragma unroll
+    for (int az = 0; az <= N; az += 2) s = fma(v[az], L.Rw64[p][az], s);
+    store_at(line_base + static_cast<size_t>(p) * stride, off, static_cast<float>(s));
+  }
+#pragma unroll
+  for (int j = 1; j <= p; ++j) {
+    double e = 0.0, o = 0.0;
+#pragma unroll
+    for (int az = 0; az <= N; ++az) {
+      if (az & 1) o = fma(v[az], L.Rw64[p + j][az], o);
+      else e = fma(v[az], L.Rw64[p + j][az], e);
+    }
+    store_at(line_base + static_cast<size_t>(p + j) * stride, off, static_cast<float>(e + o));
+    store_at(line_base + static_cast<size_t>(p - j) * stride, off, static_cast<float>(e - o));
+  }
+}
+
+// Rebuild (eq:fi with 1/alpha!) in FP64, folded in y and z, and store to the own node.
+template <int Q1, int N>
+__device__ __forceinline__ void reconstruct_store64(const LatticeConst& L, const double (&ap)[Shape<Q1, N>::M],
+                                                    float* __restrict__ out, long long stride, int node) {
+  constexpr int p = Q1 / 2;
+  constexpr int P2 = Shape<Q1, N>::P2;
+  const unsigned off = static_cast<unsigned>(node) * 4u;
+#pragma unroll 1
+  for (int ix = 0; ix < Q1; ++ix) {
+    double rx[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) rx[n] = L.Rw64[ix][n];
+    double u2[P2];
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        if (ay + az > N) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int ax = 0; ax <= N; ++ax)
+          if (ax + ay + az <= N) s = fma(ap[midx(ax, ay, az)], rx[ax], s);
+        u2[pair_pos(ay, az)] = s;
+      }
+    float* __restrict__ slab = out + static_cast<size_t>(ix * Q1 * Q1) * stride;
+    {
+      double v[N + 1];
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        double s = 0.0;
+#pragma unroll
+        for (int ay = 0; ay <= N; ay += 2)
+          if (ay + az <= N) s = fma(u2[pair_pos(ay, az)], L.Rw64[p][ay], s);
+        v[az] = s;
+      }
+      fold_line_store<Q1, N>(L, v, slab + static_cast<size_t>(p * Q1) * stride, stride, off);
+    }
+#pragma unroll
+    for (int j = 1; j <= p; ++j) {
+      double vp[N + 1], vm[N + 1];
+#pragma unroll
+      for (int az = 0; az <= N; ++az) {
+        double e = 0.0, o = 0.0;
+#pragma unroll
+        for (int ay = 0; ay <= N; ++ay) {
+          if (ay + az > N) continue;
+          if (ay & 1) o = fma(u2[pair_pos(ay, az)], L.Rw64[p + j][ay], o);
+          else e = fma(u2[pair_pos(ay, az)], L.Rw64[p + j][ay], e);
+        }
+        vp[az] = e + o;
+        vm[az] = e - o;
+      }
+      fold_line_store<Q1, N>(L, vp, slab + static_cast<size_t>((p + j) * Q1) * stride, stride, off);
+      fold_line_store<Q1, N>(L, vm, slab + static_cast<size_t>((p - j) * Q1) * stride, stride, off);
+    }
+  }
+}
+
+// Conserved moments of an FP64 projection: rho = a_0, u' = a_1 / rho,
+// theta = (sum_k a_{2e_k} + 3 rho - rho |u'|^2) / (3 rho).
+template <int N>
+__device__ __forceinline__ void sums_from_a(const double* a, const LatticeConst& L, double (&S)[5]) {
+  const double ir = 1.0 / L.r;
+  S[0] = a[0];
+  S[1] = a[midx(1, 0, 0)] * ir;
+  S[2] = a[midx(0, 1, 0)] * ir;
+  S[3] = a[midx(0, 0, 1)] * ir;
+  S[4] = (a[midx(2, 0, 0)] + a[midx(0, 2, 0)] + a[midx(0, 0, 2)] + 3.0 * a[0]) * ir * ir;
+}
+
 // Conserved moments -> rho, u' (relative to ubar), theta; validity (Sec. 4.1).
 struct Macro {
   double rho, ux, uy, uz, th;
@@ -304,30 +543,41 @@ __device__ __forceinline__ void reconstruct_store(const LatticeConst& L, const f
 
 // ------------------------------------------------------------------ kernels
 
-template <int Q1, int N, bool SHOCK>
+enum : int { kPrecFp32 = 0, kPrecFp64 = 2 };
+
+template <int Q1, int N, bool SHOCK, int PREC>
 __global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
                                                         float* __restrict__ fdst) {
   constexpr int M = Shape<Q1, N>::M;
   Pull<Q1> P;
   if (!make_pull<Q1>(L, A, P)) return;
-  float a[M];
-  double S[5];
-  gather_project<Q1, N, SHOCK>(L, A, fsrc, P, a, S);
-  const Macro mac = macro_from_sums(L, S, A.err);
   double d[M];
+  double S[5];
+  if constexpr (PREC == kPrecFp64) {
+    gather_project64<Q1, N, SHOCK>(L, A, fsrc, P, d);
+    sums_from_a<N>(d, L, S);
+  } else {
+    float a[M];
+    gather_project<Q1, N, SHOCK>(L, A, fsrc, P, a, S);
 #pragma unroll
-  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a[i]);
-  d[0] = S[0];            // orders 0 and 1 from the FP64 sums
-  d[1] = L.r * S[1];
-  d[2] = L.r * S[2];
-  d[3] = L.r * S[3];
+    for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a[i]);
+    d[0] = S[0];            // orders 0 and 1 from the FP64 sums
+    d[1] = L.r * S[1];
+    d[2] = L.r * S[2];
+    d[3] = L.r * S[3];
+  }
+  const Macro mac = macro_from_sums(L, S, A.err);
   to_local<N>(d, mac);
   relax<N>(d, L, mac.rho);
   to_lattice<N>(d, mac);
-  float ap[M];
+  if constexpr (PREC == kPrecFp64) {
+    reconstruct_store64<Q1, N>(L, d, fdst, A.stride, P.node);
+  } else {
+    float ap[M];
 #pragma unroll
-  for (int i = 0; i < M; ++i) ap[i] = static_cast<float>(d[i]);
-  reconstruct_store<Q1, N>(L, ap, fdst, A.stride, P.node);
+    for (int i = 0; i < M; ++i) ap[i] = static_cast<float>(d[i]);
+    reconstruct_store<Q1, N>(L, ap, fdst, A.stride, P.node);
+  }
 }
 
 // Moment fields of the pre-collision populations (see lbsmrt_moments).
@@ -337,17 +587,11 @@ __global__ __launch_bounds__(256) void k_moments(LatticeConst L, StepArgs A, con
   constexpr int M = Shape<Q1, N>::M;
   Pull<Q1> P;
   if (!make_pull<Q1>(L, A, P)) return;
-  float a[M];
-  double S[5];
-  gather_project<Q1, N, SHOCK>(L, A, f, P, a, S);
-  const Macro mac = macro_from_sums(L, S, A.err);
   double aa[M], d[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) aa[i] = static_cast<double>(a[i]);
-  aa[0] = S[0];
-  aa[1] = L.r * S[1];
-  aa[2] = L.r * S[2];
-  aa[3] = L.r * S[3];
+  double S[5];
+  gather_project64<Q1, N, SHOCK>(L, A, f, P, aa);
+  sums_from_a<N>(aa, L, S);
+  const Macro mac = macro_from_sums(L, S, A.err);
 #pragma unroll
   for (int i = 0; i < M; ++i) d[i] = aa[i];
   to_local<N>(d, mac);
@@ -420,15 +664,15 @@ __global__ __launch_bounds__(256) void k_equilibrium(LatticeConst L, const doubl
   shift_poly<N>(ux, th - 1.0, Ax);
   shift_poly<N>(uy, th - 1.0, Ay);
   shift_poly<N>(uz, th - 1.0, Az);
-  float a[M];
+  double a[M];
 #pragma unroll
   for (int ax = 0; ax <= N; ++ax)
 #pragma unroll
     for (int ay = 0; ay <= N; ++ay)
 #pragma unroll
       for (int az = 0; az <= N; ++az)
-        if (ax + ay + az <= N) a[midx(ax, ay, az)] = static_cast<float>(rho * Ax[ax] * Ay[ay] * Az[az]);
-  reconstruct_store<Q1, N>(L, a, f, stride, static_cast<int>(node));
+        if (ax + ay + az <= N) a[midx(ax, ay, az)] = rho * Ax[ax] * Ay[ay] * Az[az];
+  reconstruct_store64<Q1, N>(L, a, f, stride, static_cast<int>(node));
 }
 
 }  // namespace lbsmrt

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "host_setup.hpp"
+#include "adjoint_kernels.hpp"
 #include "kernels.hpp"
 #include "lbsmrt.h"
 
@@ -32,6 +33,7 @@ struct lbsmrt_ctx {
   float* d_ghost = nullptr;
   double* d_ghost_fields = nullptr;
   int* d_err = nullptr;
+  double* d_partial = nullptr;   // [n_blocks][kTauCols] per-block partial sums
   int precision = LBSMRT_FP32;
 };
 
@@ -57,11 +59,18 @@ double hermite_1d(int n, double x) {
 // Launch dispatch over the compiled (Q1, N) pairs.
 template <int Q1, int N>
 struct Launch {
-  static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
+  template <int PREC>
+  static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
     if (c->shock)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src, dst);
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, PREC>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src,
+                         dst);
     else
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src, dst);
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, false, PREC>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src,
+                         dst);
+  }
+  static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
+    if (c->precision == LBSMRT_FP32) step_p<kPrecFp32>(c, A, src, dst, s);
+    else step_p<kPrecFp64>(c, A, src, dst, s);
   }
   static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s) {
     if (c->shock)
@@ -70,6 +79,24 @@ struct Launch {
     else
       hipLaunchKernelGGL((k_moments<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, out, mask,
                          c->n_nodes);
+  }
+  static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
+                      hipStream_t s) {
+    if (c->shock)
+      hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f_t, lam_next,
+                         lam_t, c->d_partial);
+    else
+      hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f_t, lam_next,
+                         lam_t, c->d_partial);
+  }
+  static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
+                        float* lam, hipStream_t s) {
+    if (c->shock)
+      hipLaunchKernelGGL((k_loss_seed<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, target,
+                         c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
+    else
+      hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, target,
+                         c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
   }
   static void equilibrium(lbsmrt_ctx* c, const double* fields, long long count, float* f, long long stride,
                           hipStream_t s) {
@@ -109,6 +136,7 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_ghost);
   (void)hipFree(c->d_ghost_fields);
   (void)hipFree(c->d_err);
+  (void)hipFree(c->d_partial);
   delete c;
 }
 
@@ -117,7 +145,7 @@ lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
   if (d->n_abscissa < 1 || d->n_abscissa > 8) return LBSMRT_E_ARG;
   if (d->order_N < 2 || d->order_N > kMaxN) return LBSMRT_E_ARG;
   if (d->regularized != 1) return LBSMRT_E_UNSUPPORTED;
-  if (d->precision != LBSMRT_FP32) return LBSMRT_E_UNSUPPORTED;
+  if (d->precision != LBSMRT_FP32 && d->precision != LBSMRT_FP64_CONTRACT) return LBSMRT_E_UNSUPPORTED;
   if (!(d->rho_ref > 0.0)) return LBSMRT_E_ARG;
   for (int n = 2; n <= d->order_N; ++n)
     for (int m = 0; 2 * m <= n; ++m) {
@@ -193,6 +221,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       const double h = hermite_1d(n, cj);
       L.He[j][n] = static_cast<float>(h);
       L.Rw[j][n] = static_cast<float>(c->w1[j] * h / fact);
+      L.He64[j][n] = h;
+      L.Rw64[j][n] = c->w1[j] * h / fact;
     }
   }
   L.r = r;
@@ -249,6 +279,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (hipMalloc(&c->d_ghost, sizeof(float) * c->Q * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_ghost_fields, sizeof(double) * 5 * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_partial, sizeof(double) * kTauCols * static_cast<size_t>(c->n_blocks)) != hipSuccess)
+    return fail(LBSMRT_E_NOMEM);
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
   std::vector<double> gf(5 * c->n_ghost, 0.0);
   for (int i = 0; i < n_domains; ++i) {
@@ -337,16 +369,37 @@ lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* c, const double* fields, float* f, 
 
 lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* lam_next, float* lam_t,
                                   double* dL_dtau, void* stream) {
-  (void)stream;
-  if (!c || !f_t || !lam_next || !lam_t || !dL_dtau || lam_t == lam_next) return LBSMRT_E_ARG;
-  return LBSMRT_E_UNSUPPORTED;
+  if (!c || !f_t || !lam_next || !lam_t || !dL_dtau) return LBSMRT_E_ARG;
+  if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const StepArgs A = step_args(c);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, s); });
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, c->d_partial, c->n_blocks, kTauCols, dL_dtau, 1);
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 
 lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* c, const float* f, const double* target, const double* scales, float* lam,
                                double* loss, void* stream) {
-  (void)stream;
-  if (!c || !f || !target || !scales || !lam || !loss) return LBSMRT_E_ARG;
-  return LBSMRT_E_UNSUPPORTED;
+  if (!c || !f || !target || !scales || !lam || !loss || lam == f) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const StepArgs A = step_args(c);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::loss_seed(c, A, f, target, scales, lam, s); });
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, c->d_partial, c->n_blocks, 1, loss, 0);
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* c, const double* tau) {
+  if (!c || !tau) return LBSMRT_E_ARG;
+  for (int n = 2; n <= c->N; ++n)
+    for (int m = 0; 2 * m <= n; ++m) {
+      if (n == 2 && m == 1) continue;
+      const double t = tau[n * 3 + m];
+      if (!(t > 0.0) || !std::isfinite(t)) return LBSMRT_E_ARG;
+    }
+  for (int n = 2; n <= c->N; ++n)
+    for (int m = 0; 2 * m <= n; ++m)
+      if (!(n == 2 && m == 1)) c->L.tau[n][m] = tau[n * 3 + m];
+  return LBSMRT_OK;
 }
 
 lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* c, void* stream) {

@@ -52,6 +52,8 @@ __host__ __device__ constexpr double coefD(int n, int m) {
 struct LatticeConst {
   float  He[kMaxQ1][kMaxN + 1];   // He_n(c_j), c_j = r e_j
   float  Rw[kMaxQ1][kMaxN + 1];   // w_j He_n(c_j) / n!
+  double He64[kMaxQ1][kMaxN + 1]; // the same two tables in FP64
+  double Rw64[kMaxQ1][kMaxN + 1];
   int    e[kMaxQ1];               // 1D integers, ascending
   double r;                       // lattice constant c_l
   int    k[3];                    // frame shift, ubar = r k
@@ -60,6 +62,11 @@ struct LatticeConst {
   double tau_offset;              // 0.5 or 0
   int    density_scaling;
 };
+
+// He_n(0): 0 for odd n, (-1)^(n/2) (n-1)!! for even n
+__host__ __device__ constexpr double hermite_at_zero(int n) {
+  return (n & 1) ? 0.0 : (((n / 2) & 1) ? -1.0 : 1.0) * dfact(n - 1);
+}
 
 // ------------------------------------------------------------------ tensor algebra
 // trace: rank L+2 -> rank L,   (tr X)_alpha = sum_k X_{alpha + 2 e_k}

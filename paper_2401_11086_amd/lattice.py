@@ -48,7 +48,7 @@ class Lattice:
         d.tau_density_scaling = int(bool(tau_density_scaling))
         d.tau_offset_half = int(bool(tau_offset_half))
         d.regularized = 1
-        d.precision = {"fp32": C.FP32, "split_bf16x3": C.SPLIT_BF16X3}[precision]
+        d.precision = {"fp32": C.FP32, "split_bf16x3": C.SPLIT_BF16X3, "fp64_contract": C.FP64_CONTRACT}[precision]
         arr = (C.DomainDesc * len(domains))()
         for i, dom in enumerate(domains):
             x = arr[i]
@@ -121,6 +121,15 @@ class Lattice:
                                          _dev_ptr(lam, torch.float32, "lam"), _dev_ptr(loss, torch.float64, "loss"),
                                          _stream_ptr()), "lbsmrt_loss_seed")
         return lam
+
+    def set_tau(self, tau):
+        """Replace the relaxation times ({(n, m): tau_nm}); missing entries keep their value."""
+        self.tau.update({k: float(v) for k, v in tau.items()})
+        arr = (ctypes.c_double * 18)()
+        for n in range(6):
+            for m in range(3):
+                arr[n * 3 + m] = float(self.tau.get((n, m), 1.0))
+        C.check(C.lib().lbsmrt_set_tau(self._h, arr), "lbsmrt_set_tau")
 
     def sync(self):
         """Wait for the current stream; raise if a node left the validity region."""

@@ -24,9 +24,12 @@ def torch():
     return t
 
 
-def _lattice(case):
+PRECISIONS = ["fp32", "fp64_contract"]
+
+
+def _lattice(case, precision="fp32"):
     from paper_2401_11086_amd import Lattice
-    return Lattice(**case["lat_kw"])
+    return Lattice(precision=precision, **case["lat_kw"])
 
 
 def _gpu_state(torch, lat, case, noise_seed=None, amp=0.02):
@@ -109,10 +112,11 @@ def test_equilibrium_fill_matches_oracle(torch, name):
     assert err < 1e-6, err
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("name", list(CASES))
-def test_one_step_matches_oracle(torch, name):
+def test_one_step_matches_oracle(torch, name, precision):
     case = CASES[name]()
-    lat = _lattice(case)
+    lat = _lattice(case, precision)
     f0 = _gpu_state(torch, lat, case, noise_seed=1)
     fo0 = oracle_state_from_gpu(_host(f0), case)
     _compare_observables(lat, f0, fo0, case, TOL_STEP)
@@ -144,7 +148,8 @@ def _shift_profile(y, dx):
     return np.interp(x + dx, x, y)
 
 
-def test_shock_trajectory_1000_steps_matches_oracle(torch):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_shock_trajectory_1000_steps_matches_oracle(torch, precision):
     """Ma = 1.2, D3Q343, N = 4, Nx = 200: normalised rho, theta, q_x every 100 steps.
     A shock between two fixed Maxwellian ends is translation-neutral: FP32
     round-off in the mass balance moves it without a restoring force, so the
@@ -152,7 +157,7 @@ def test_shock_trajectory_1000_steps_matches_oracle(torch):
     (unaligned) difference and the drift are reported."""
     from paper_2401_11086_amd import _lib as C
     case = shock_case(1.2, 200, D1Q7, 4)
-    lat = _lattice(case)
+    lat = _lattice(case, precision)
     fa = _gpu_state(torch, lat, case)
     fb = lat.new_state()
     fo = oracle_state_from_gpu(_host(fa), case)
@@ -180,10 +185,11 @@ def test_shock_trajectory_1000_steps_matches_oracle(torch):
     print(f"worst aligned normalised-profile error over 1000 steps: {worst:.3e}")
 
 
-def test_box_trajectory_matches_oracle(torch):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_box_trajectory_matches_oracle(torch, precision):
     """12^3 periodic Fourier box, 20 steps: every moment family within 1e-4."""
     case = box_case(12, D1Q7, 4, n_ref=32)
-    lat = _lattice(case)
+    lat = _lattice(case, precision)
     fa = _gpu_state(torch, lat, case)
     fb = lat.new_state()
     fo = oracle_state_from_gpu(_host(fa), case)
@@ -209,9 +215,10 @@ def test_invalid_state_is_reported(torch):
     lat.sync()   # the flag was cleared by the read
 
 
-def test_step_is_bitwise_deterministic(torch):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_step_is_bitwise_deterministic(torch, precision):
     case = box_case(10, D1Q7, 4)
-    lat = _lattice(case)
+    lat = _lattice(case, precision)
     f0 = _gpu_state(torch, lat, case, noise_seed=3)
     a, b = lat.new_state(), lat.new_state()
     lat.step(f0, a, 1)
@@ -219,3 +226,30 @@ def test_step_is_bitwise_deterministic(torch):
     lat.sync()
     n = lat.n_nodes
     assert torch.equal(a[:, :n], b[:, :n])
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_box_conserves_mass_momentum_energy(torch, precision):
+    """Periodic box: total mass, momentum and energy after 50 steps.  The FP64
+    contraction path conserves them up to the float32 rounding of the stored f."""
+    from paper_2401_11086_amd import _lib as C
+    case = box_case(16, D1Q7, 4, n_ref=64)
+    lat = _lattice(case, precision)
+    fa = _gpu_state(torch, lat, case, noise_seed=5, amp=0.01)
+    fb = lat.new_state()
+
+    def totals(f):
+        m = lat.moments(f, C.MOM_BASIC).double()
+        rho, u, th = m[0], m[1:4], m[4]
+        return [float(rho.sum()), *[float((rho * u[k]).sum()) for k in range(3)],
+                float((rho * (3 * th + (u * u).sum(0))).sum())]
+    t0 = totals(fa)
+    cur = lat.step(fa, fb, 50)
+    lat.sync()
+    t1 = totals(cur)
+    n = lat.n_nodes
+    drift = [abs(b - a) / n for a, b in zip(t0, t1)]
+    print(f"{precision}: per-node drift of mass, momentum, energy over 50 steps: {drift}")
+    # FP32 contractions carry the float32 rounding of the rebuild tables (~2e-8 relative per step)
+    bound = 2e-7 if precision == "fp64_contract" else 2e-5
+    assert max(drift) < bound, drift
