@@ -86,6 +86,48 @@ def copy_calibration(torch, n_floats, steps, warmup):
                       "bytes_per_launch": 8 * n_floats, "ms_per_copy": round(ms, 4), "steps": steps}), flush=True)
 
 
+def _time_steps(torch, fn, n):
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(torch.cuda.current_stream())
+    for _ in range(n):
+        fn()
+    ev1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / n
+
+
+def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
+    """Same workload: the other contraction precision, and the adjoint step
+    (lbsmrt_step_adjoint on its own, and with the forward replay a checkpointed
+    reverse sweep adds per step)."""
+    from paper_2401_11086_amd import Lattice
+    out = {}
+    steps = max(4, args.steps // 2)
+    other = "fp32" if args.precision == "fp64_contract" else "fp64_contract"
+    lat2 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision=other)
+    lat2.step(fa, fb, 2)
+    ms = _time_steps(torch, lambda: lat2.step(fa, fb, 1), steps)
+    lat2.sync()
+    out[other] = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2)}
+    lat2.close()
+    _progress(f"{other}: {ms:.3f} ms/step")
+    lam_a, lam_b = lat.new_state(), lat.new_state()
+    lam_a.normal_()
+    dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
+    lat.step_adjoint(fa, lam_a, lam_b, dtau)
+    ms_adj = _time_steps(torch, lambda: lat.step_adjoint(fa, lam_a, lam_b, dtau), steps)
+    lat.sync()
+    assert torch.isfinite(dtau).all()
+    _progress(f"adjoint: {ms_adj:.3f} ms/step ({ms_adj / ms_fwd:.2f}x forward)")
+    out["adjoint"] = {"ms_per_step": round(ms_adj, 4), "ratio_to_forward": round(ms_adj / ms_fwd, 3),
+                      "reverse_sweep_ratio_with_replay": round((ms_adj + ms_fwd) / ms_fwd, 3),
+                      "bytes_per_launch": 12.0 * lat.Q * lat.n_nodes,
+                      "achieved_GBs": round(12.0 * lat.Q * lat.n_nodes / (ms_adj / 1e3) / 1e9, 1)}
+    del lam_a, lam_b
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +137,8 @@ def main():
     ap.add_argument("--kn", type=float, default=0.05)
     ap.add_argument("--precision", default="fp64_contract", choices=["fp32", "fp64_contract"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32-contraction and adjoint timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain device copy of one f buffer instead (HBM calibration)")
     args = ap.parse_args()
@@ -149,6 +193,9 @@ def main():
     _progress(f"{ms_step:.3f} ms/step, {mlups:.1f} MLUPS, {achieved:.0f} GB/s (wall {wall:.2f} s)")
     rho = lat.moments(cur)[0]
     assert torch.isfinite(rho).all() and abs(float(rho.mean()) - 1.0) < 1e-3
+    variants = {}
+    if not args.no_variants:
+        variants = time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step)
 
     out = {
         "metric": "MLUPS & % HBM/MFMA roofline, SMRT collide-stream; FP32 vs split-BF16; adjoint",
@@ -172,6 +219,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": f"k_collide_stream<{lat.Q1},{N}>", "bytes_per_launch": bytes_per_launch},
     }
+    if variants:
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         _progress("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(ab, deg, N, edge, args.kn)

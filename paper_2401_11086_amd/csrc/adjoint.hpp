@@ -157,81 +157,69 @@ __device__ __forceinline__ void axis_transform_T(double* d, const double (&P)[N 
       }
 }
 
-__host__ __device__ constexpr int order_of(int i) {
-  int n = 0;
-  while (order_start(n + 1) <= i) ++n;
-  return n;
+// Compact index of the relaxation times that act: (2,0), (3,0), (3,1), (4,0), (4,1), (4,2), (5,0), (5,1), (5,2).
+__host__ __device__ constexpr int tau_slot(int n, int m) { return n == 2 ? 0 : (n == 3 ? 1 + m : (n == 4 ? 3 + m : 6 + m)); }
+__host__ __device__ constexpr int n_tau_slots(int N) { return N == 2 ? 1 : (N == 3 ? 3 : (N == 4 ? 6 : 9)); }
+
+// Multiplicity n!/(a! b! c!) of component (a,b,c) of a symmetric tensor: the weight of the
+// full-contraction inner product in the component representation.
+__host__ __device__ constexpr double multiplicity(int a, int b, int c) {
+  return factorial(a + b + c) / (factorial(a) * factorial(b) * factorial(c));
 }
 
-// Decode multi-index i -> (a,b,c)
-__host__ __device__ constexpr int mi_a(int i) {
-  const int n = order_of(i);
-  const int r = i - order_start(n);
-  int a = n;
-  int rem = r;
-  while (rem >= n - a + 1) { rem -= n - a + 1; --a; }
-  return a;
-}
-__host__ __device__ constexpr int mi_b(int i) {
-  const int n = order_of(i);
-  const int r = i - order_start(n);
-  int a = n;
-  int rem = r;
-  while (rem >= n - a + 1) { rem -= n - a + 1; --a; }
-  return (n - a) - rem;
-}
-__host__ __device__ constexpr int mi_c(int i) { return order_of(i) - mi_a(i) - mi_b(i); }
-
-// Per-node reverse sweep.  d: local moments entering the relaxation (d_0 = rho, d_1 = 0).
-// ab: in dL/da' (lattice frame, after collision); out dL/da (lattice frame, before).
-// tb[n][m] += dL/dtau_nm.
-template <int N>
-__device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro& mac, const double* d, double* ab,
-                                             double (&tb)[kMaxN + 1][3]) {
+// Per-node reverse sweep.
+//   dv: local moments d entering the relaxation (d_0 = rho, d_1 = 0), per work-item in LDS;
+//   zv: per work-item LDS scratch of M doubles (receives z = Lambda d');
+//   ab: in dL/da' (lattice frame, after collision); out dL/da (lattice frame, before);
+//   tb[tau_slot(n,m)] += dL/dtau_nm.
+// Two identities keep a single M-vector in registers:
+//  * the shift operators commute with the raising operator (L y)_b = b y_{b-1}, so
+//    dT_A/du_k = L_k T_A = T_A L_k and dT_A/dtheta = T_A (1/2) sum_k L_k^2: the u and theta
+//    sensitivities of a' = T_A z are zbar . (L_k z) and zbar . (sum_k L_k^2 z)/2 with zbar = T_A^T abar;
+//  * the irreducible projectors are self-adjoint in the full-contraction inner product
+//    (weights W = n!/alpha!), so the transposed relaxation is W K W^{-1}.
+template <int N, class V>
+__device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro& mac, const V& dv, const V& zv,
+                                             double* ab, double* tb) {
   constexpr int M = n_moments(N);
   const double rho = mac.rho, th = mac.th;
   const double u[3] = {mac.ux, mac.uy, mac.uz};
   const double sc = L.density_scaling ? L.rho_ref / rho : 1.0;
-  double om[kMaxN + 1][3];
-#pragma unroll
-  for (int n = 2; n <= N; ++n)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) om[n][m] = (2 * m <= n) ? 1.0 / fma(L.tau[n][m], sc, L.tau_offset) : 0.0;
-  om[2][1] = 0.0;
-
   double ubar[3] = {0.0, 0.0, 0.0};
   double thbar = 0.0, rhobar = 0.0;
-  // powers of sqrt(theta)
   const double sq = sqrt(th);
   double sp[N + 1];
   sp[0] = 1.0;
 #pragma unroll
   for (int n = 1; n <= N; ++n) sp[n] = sp[n - 1] * sq;
+  auto omegas = [&](int n, double (&om)[3]) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) om[m] = (2 * m <= n) ? 1.0 / fma(L.tau[n][m], sc, L.tau_offset) : 0.0;
+    if (n == 2) om[1] = 0.0;   // the (2,1) part is left unrelaxed (it is zero)
+  };
 
-  // ---- a' = T_A Lambda d'  (reverse)
+  // ---- z = Lambda d' = Lambda K d, into LDS
+  zv.set(0, dv(0));
+  zv.set(1, 0.0);
+  zv.set(2, 0.0);
+  zv.set(3, 0.0);
+#pragma unroll
+  for (int n = 2; n <= N; ++n) {
+    double om[3];
+    omegas(n, om);
+    double t[n_sym(kMaxN)];
+#pragma unroll
+    for (int i = 0; i < n_sym(n); ++i) t[i] = dv(order_start(n) + i);
+    if (n == 2) relax_order<2>(t, om);
+    if (n == 3) relax_order<3>(t, om);
+    if constexpr (N >= 4) if (n == 4) relax_order<4>(t, om);
+    if constexpr (N >= 5) if (n == 5) relax_order<5>(t, om);
+#pragma unroll
+    for (int i = 0; i < n_sym(n); ++i) zv.set(order_start(n) + i, t[i] * sp[n]);
+  }
+
+  // ---- a' = T_A z  (reverse): zbar = T_A^T abar; u, theta sensitivities in z space
   {
-    double dp[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) dp[i] = d[i];
-    relax<N>(dp, L, rho);
-    double ap[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) ap[i] = dp[i];
-    to_lattice<N>(ap, mac);
-    // u, theta through T_A
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const int a = mi_a(i), b = mi_b(i), c = mi_c(i);
-      const double g = ab[i];
-      if (a >= 1) ubar[0] += g * a * ap[midx(a - 1, b, c)];
-      if (b >= 1) ubar[1] += g * b * ap[midx(a, b - 1, c)];
-      if (c >= 1) ubar[2] += g * c * ap[midx(a, b, c - 1)];
-      double t = 0.0;
-      if (a >= 2) t += binom(a, 2) * ap[midx(a - 2, b, c)];
-      if (b >= 2) t += binom(b, 2) * ap[midx(a, b - 2, c)];
-      if (c >= 2) t += binom(c, 2) * ap[midx(a, b, c - 2)];
-      thbar += g * t;
-    }
     double Ax[N + 1], Ay[N + 1], Az[N + 1];
     shift_poly<N>(mac.ux, th - 1.0, Ax);
     shift_poly<N>(mac.uy, th - 1.0, Ay);
@@ -239,34 +227,89 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     axis_transform_T<N, 2>(ab, Az);
     axis_transform_T<N, 1>(ab, Ay);
     axis_transform_T<N, 0>(ab, Ax);
-    // theta through Lambda; then d'bar = Lambda zbar
+  }
+  {
+    const double i2th = 0.5 / th;
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const int n = order_of(i);
-      if (n >= 1) thbar += ab[i] * (0.5 * n) * (sp[n] / th) * dp[i];
-      ab[i] *= sp[n];
+    for (int a = 0; a <= N; ++a)
+#pragma unroll
+    for (int b = 0; b <= N; ++b)
+#pragma unroll
+    for (int c = 0; c <= N; ++c) {
+      const int n = a + b + c;
+      if (n == 0 || n > N) continue;
+      const int i = midx(a, b, c);
+      const double g = ab[i];
+      if (a >= 1) ubar[0] += g * a * zv(midx(a - 1, b, c));
+      if (b >= 1) ubar[1] += g * b * zv(midx(a, b - 1, c));
+      if (c >= 1) ubar[2] += g * c * zv(midx(a, b, c - 1));
+      double t = (n * i2th) * zv(i);
+      if (a >= 2) t += binom(a, 2) * zv(midx(a - 2, b, c));
+      if (b >= 2) t += binom(b, 2) * zv(midx(a, b - 2, c));
+      if (c >= 2) t += binom(c, 2) * zv(midx(a, b, c - 2));
+      thbar += g * t;
     }
   }
-  // orders 0 and 1 of d' are rho and 0
+  // d'bar = Lambda zbar; orders 0 and 1 of d' are rho and 0
+#pragma unroll
+  for (int n = 2; n <= N; ++n)
+#pragma unroll
+    for (int i = order_start(n); i < order_start(n + 1); ++i) ab[i] *= sp[n];
   rhobar += ab[0];
-  ab[0] = 0.0;
-  ab[1] = ab[2] = ab[3] = 0.0;
+  ab[0] = ab[1] = ab[2] = ab[3] = 0.0;
 
-  // ---- relaxation (reverse)
+  // ---- relaxation (reverse):  dbar = W K W^{-1} d'bar,  omega_bar_m = -<P_m y, d>_W with y = W^{-1} d'bar
 #pragma unroll
   for (int n = 2; n <= N; ++n) {
+    double om[3];
+    omegas(n, om);
+    constexpr int S = n_sym(kMaxN);
+    double y[S], wgt[S];
+#pragma unroll
+    for (int a = 0; a <= n; ++a)
+#pragma unroll
+      for (int b = 0; b <= n; ++b)
+        if (a + b <= n) wgt[sym_pos(n, a, b)] = multiplicity(a, b, n - a - b);
+#pragma unroll
+    for (int i = 0; i < n_sym(n); ++i) y[i] = ab[order_start(n) + i] / wgt[i];
     double ob[3] = {0.0, 0.0, 0.0};
-    double* dpb = ab + order_start(n);
-    const double* dn = d + order_start(n);
-    if (n == 2) relax_order_T<2>(dpb, dn, om[2], ob);
-    if (n == 3) relax_order_T<3>(dpb, dn, om[3], ob);
-    if constexpr (N >= 4) if (n == 4) relax_order_T<4>(dpb, dn, om[4], ob);
-    if constexpr (N >= 5) if (n == 5) relax_order_T<5>(dpb, dn, om[5], ob);
+    double r[S];
+#pragma unroll
+    for (int i = 0; i < n_sym(n); ++i) r[i] = (1.0 - om[0]) * y[i];
+    double p0d = 0.0;   // <y, d>_W
+#pragma unroll
+    for (int i = 0; i < n_sym(n); ++i) p0d += wgt[i] * y[i] * dv(order_start(n) + i);
+#pragma unroll
+    for (int m = 1; m <= 2; ++m) {
+      if (2 * m > n) continue;
+      double P[S];
+      if (n == 2 && m == 1) irreducible_piece<2, 1>(y, P);
+      if (n == 3 && m == 1) irreducible_piece<3, 1>(y, P);
+      if constexpr (N >= 4) {
+        if (n == 4 && m == 1) irreducible_piece<4, 1>(y, P);
+        if (n == 4 && m == 2) irreducible_piece<4, 2>(y, P);
+      }
+      if constexpr (N >= 5) {
+        if (n == 5 && m == 1) irreducible_piece<5, 1>(y, P);
+        if (n == 5 && m == 2) irreducible_piece<5, 2>(y, P);
+      }
+      double pd = 0.0;
+#pragma unroll
+      for (int i = 0; i < n_sym(n); ++i) pd += wgt[i] * P[i] * dv(order_start(n) + i);
+      ob[m] = -pd;
+      p0d -= pd;
+      const double cm = om[m] - om[0];
+#pragma unroll
+      for (int i = 0; i < n_sym(n); ++i) r[i] -= cm * P[i];
+    }
+    ob[0] = -p0d;
+#pragma unroll
+    for (int i = 0; i < n_sym(n); ++i) ab[order_start(n) + i] = r[i] * wgt[i];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (2 * m > n || (n == 2 && m == 1)) continue;
-      const double w = om[n][m];
-      tb[n][m] += ob[m] * (-sc * w * w);
+      const double w = om[m];
+      tb[tau_slot(n, m)] += ob[m] * (-sc * w * w);
       if (L.density_scaling) rhobar += ob[m] * (w * w * L.tau[n][m] * L.rho_ref / (rho * rho));
     }
   }
@@ -276,21 +319,30 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     const double ith = 1.0 / th;
     const double isq = 1.0 / sq;
 #pragma unroll
-    for (int i = 4; i < M; ++i) {
-      const int a = mi_a(i), b = mi_b(i), c = mi_c(i);
+    for (int a = 0; a <= N; ++a)
+#pragma unroll
+    for (int b = 0; b <= N; ++b)
+#pragma unroll
+    for (int c = 0; c <= N; ++c) {
       const int n = a + b + c;
+      if (n < 2 || n > N) continue;
+      const int i = midx(a, b, c);
       const double g = ab[i];
-      if (a >= 1) ubar[0] -= isq * g * a * d[midx(a - 1, b, c)];
-      if (b >= 1) ubar[1] -= isq * g * b * d[midx(a, b - 1, c)];
-      if (c >= 1) ubar[2] -= isq * g * c * d[midx(a, b, c - 1)];
+      if (a >= 1) ubar[0] -= isq * g * a * dv(midx(a - 1, b, c));
+      if (b >= 1) ubar[1] -= isq * g * b * dv(midx(a, b - 1, c));
+      if (c >= 1) ubar[2] -= isq * g * c * dv(midx(a, b, c - 1));
       double t = 0.0;
-      if (a >= 2) t += binom(a, 2) * d[midx(a - 2, b, c)];
-      if (b >= 2) t += binom(b, 2) * d[midx(a, b - 2, c)];
-      if (c >= 2) t += binom(c, 2) * d[midx(a, b, c - 2)];
-      thbar -= g * ((0.5 * n) * ith * d[i] + ith * t);
+      if (a >= 2) t += binom(a, 2) * dv(midx(a - 2, b, c));
+      if (b >= 2) t += binom(b, 2) * dv(midx(a, b - 2, c));
+      if (c >= 2) t += binom(c, 2) * dv(midx(a, b, c - 2));
+      thbar -= g * ((0.5 * n) * ith * dv(i) + ith * t);
     }
 #pragma unroll
-    for (int i = 4; i < M; ++i) ab[i] /= sp[order_of(i)];
+    for (int n = 2; n <= N; ++n) {
+      const double inv = 1.0 / sp[n];
+#pragma unroll
+      for (int i = order_start(n); i < order_start(n + 1); ++i) ab[i] *= inv;
+    }
     double Bx[N + 1], By[N + 1], Bz[N + 1];
     shift_poly<N>(-mac.ux, 1.0 - th, Bx);
     shift_poly<N>(-mac.uy, 1.0 - th, By);

@@ -9,7 +9,7 @@ constexpr int kTauCols = (kMaxN + 1) * 3;   // dL/dtau[n][m] flattened as n*3+m
 // Scatter of mu = P^T abar to the streaming sources: out[q][x - s_q] = sum_alpha He_alpha(c_q) abar_alpha.
 // Populations whose source was a ghost cell (shock ends) are skipped.
 template <int Q1, int N, bool SHOCK>
-__device__ __forceinline__ void scatter_transpose_projection(const LatticeConst& L, const Pull<Q1>& P,
+LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull<Q1>& P,
                                                              const double (&ab)[n_moments(N)],
                                                              float* __restrict__ out, long long stride) {
   constexpr int p = Q1 / 2;
@@ -119,41 +119,87 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return out;
 }
 
+// Per-thread vector of M doubles in dynamic LDS, strided by the block size (conflict-free).
+struct LdsVec {
+  double* base;
+  int stride;
+  __device__ __forceinline__ double operator()(int i) const { return base[i * stride]; }
+  __device__ __forceinline__ void set(int i, double v) const { base[i * stride] = v; }
+};
+
 // One adjoint step: lam_t = (d f_{t+1} / d f_t)^T lam_next, per-block partials of dL/dtau.
+// Dynamic LDS: 2 M doubles per work-item (the local moments d and z = Lambda d').
 template <int Q1, int N, bool SHOCK>
 __global__ __launch_bounds__(256) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
                                                  const float* __restrict__ lam_next, float* __restrict__ lam_t,
                                                  double* __restrict__ partial) {
   constexpr int M = n_moments(N);
+  constexpr int NT = n_tau_slots(N);
+  extern __shared__ double lds[];
   __shared__ double red[256];
   Pull<Q1> P;
   const bool active = make_pull<Q1>(L, A, P);
-  double tb[kMaxN + 1][3];
+  double tb[NT];
 #pragma unroll
-  for (int n = 0; n <= kMaxN; ++n)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) tb[n][m] = 0.0;
+  for (int i = 0; i < NT; ++i) tb[i] = 0.0;
   if (active) {
-    double d[M];
-    double S[5];
-    gather_project64<Q1, N, SHOCK>(L, A, f_t, P, d);
-    sums_from_a<N>(d, L, S);
-    const Macro mac = macro_from_sums(L, S, A.err);
-    to_local<N>(d, mac);
+    const LdsVec dv{lds + threadIdx.x, static_cast<int>(blockDim.x)};
+    const LdsVec zv{lds + static_cast<size_t>(M) * blockDim.x + threadIdx.x, static_cast<int>(blockDim.x)};
+    Macro mac;
+    {
+      double d[M];
+      double S[5];
+      gather_project64<Q1, N, SHOCK>(L, A, f_t, P, d);
+      sums_from_a<N>(d, L, S);
+      mac = macro_from_sums(L, S, A.err);
+      to_local<N>(d, mac);
+#pragma unroll
+      for (int i = 0; i < M; ++i) dv.set(i, d[i]);
+    }
     double ab[M];
     own_project64<Q1, N, true>(L, lam_next, A.stride, P.node, ab);
-    node_adjoint<N>(L, mac, d, ab, tb);
+    node_adjoint<N>(L, mac, dv, zv, ab, tb);
     scatter_transpose_projection<Q1, N, SHOCK>(L, P, ab, lam_t, A.stride);
     if (SHOCK && P.bc_x == 1) zero_outflow<Q1>(L, P, lam_t, A.stride);
   }
 #pragma unroll
-  for (int n = 0; n <= kMaxN; ++n)
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const bool used = n >= 2 && n <= N && 2 * m <= n && !(n == 2 && m == 1);
-      const double s = used ? block_sum(tb[n][m], red) : 0.0;
-      if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * kTauCols + n * 3 + m] = s;
-    }
+  for (int i = 0; i < NT; ++i) {
+    const double s = block_sum(tb[i], red);
+    if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * NT + i] = s;
+  }
+}
+
+// Deterministic two-stage column sums of per-block partials [rows][cols].
+// Stage 1 (kReduceBlocks work-groups of 256): work-group g sums rows g, g + G, g + 2G, ... per
+// thread in a fixed order, then a fixed tree; writes stage[g][col].
+constexpr int kReduceBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_reduce_stage1(const double* __restrict__ partial, int rows, int cols,
+                                                       double* __restrict__ stage) {
+  __shared__ double red[256];
+  for (int c = 0; c < cols; ++c) {
+    double s = 0.0;
+    for (int r = blockIdx.x + gridDim.x * static_cast<int>(threadIdx.x); r < rows;
+         r += gridDim.x * static_cast<int>(blockDim.x))
+      s += partial[static_cast<size_t>(r) * cols + c];
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) stage[static_cast<size_t>(blockIdx.x) * cols + c] = t;
+  }
+}
+
+// Stage 2 for dL/dtau: out[n*3+m] += sum_g stage[g][tau_slot(n,m)] in order.
+template <int N>
+__global__ void k_reduce_tau(const double* __restrict__ stage, int groups, double* __restrict__ out) {
+  constexpr int NT = n_tau_slots(N);
+  const int c = threadIdx.x;
+  if (c >= NT) return;
+  double s = 0.0;
+  for (int g = 0; g < groups; ++g) s += stage[static_cast<size_t>(g) * NT + c];
+  int n = 2, m = 0;
+  for (int nn = 2; nn <= N; ++nn)
+    for (int mm = 0; 2 * mm <= nn; ++mm)
+      if (!(nn == 2 && mm == 1) && tau_slot(nn, mm) == c) { n = nn; m = mm; }
+  out[n * 3 + m] += s;
 }
 
 // Seed of the adjoint for L = sum_x [s0^2 (rho - rho*)^2 + s1^2 (theta - theta*)^2 + s2^2 (q_x - q_x*)^2]
@@ -216,13 +262,13 @@ __global__ __launch_bounds__(256) void k_loss_seed(LatticeConst L, StepArgs A, c
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// out[c] (+)= sum_b partial[b * cols + c] in block order (deterministic).
-__global__ void k_reduce_partials(const double* __restrict__ partial, int n_blocks, int cols, double* __restrict__ out,
+// Stage 2 for plain columns: out[c] (+)= sum_g stage[g][c] in order.
+__global__ void k_reduce_partials(const double* __restrict__ stage, int groups, int cols, double* __restrict__ out,
                                   int accumulate) {
   const int c = threadIdx.x;
   if (c >= cols) return;
   double s = 0.0;
-  for (int b = 0; b < n_blocks; ++b) s += partial[static_cast<size_t>(b) * cols + c];
+  for (int g = 0; g < groups; ++g) s += stage[static_cast<size_t>(g) * cols + c];
   out[c] = accumulate ? out[c] + s : s;
 }
 

@@ -33,6 +33,7 @@ struct StepArgs {
   int n_ghost;
   long long stride;
   int* err;
+  double* dtau;              // adjoint only: dL/dtau [6][3]
 };
 
 enum : int { kErrState = 1 };
@@ -261,7 +262,7 @@ __device__ __forceinline__ void fold_slab_project(const LatticeConst& L, const f
 // FP64 projection of a node's own populations (no streaming) with table T:
 //   out[ax,ay,az] = sum_{ix,iy,iz} T_ax(c_ix) T_ay(c_iy) T_az(c_iz) v[q]
 template <int Q1, int N, bool RW>
-__device__ __forceinline__ void own_project64(const LatticeConst& L, const float* __restrict__ v, long long stride,
+LBSMRT_PHASE void own_project64(const LatticeConst& L, const float* __restrict__ v, long long stride,
                                               int node, double (&out)[n_moments(N)]) {
   constexpr int P2 = n_sym(N);
   const unsigned off = static_cast<unsigned>(node) * 4u;
@@ -291,7 +292,7 @@ __device__ __forceinline__ void own_project64(const LatticeConst& L, const float
 // Gather + FP64 projection (eq:an): a[ax,ay,az] = sum_ix He_ax(c_ix) t2_ix[ay,az].
 // rho = a_0, j = a_1 and sum g |c|^2 = sum_k a_{2 e_k} + 3 rho come out exactly in FP64.
 template <int Q1, int N, bool SHOCK>
-__device__ __forceinline__ void gather_project64(const LatticeConst& L, const StepArgs& A,
+LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
                                                  const float* __restrict__ f, const Pull<Q1>& P,
                                                  double (&a)[Shape<Q1, N>::M]) {
   constexpr int P2 = Shape<Q1, N>::P2;
@@ -361,7 +362,7 @@ __device__ __forceinline__ void fold_line_store(const LatticeConst& L, const dou
 
 // Rebuild (eq:fi with 1/alpha!) in FP64, folded in y and z, and store to the own node.
 template <int Q1, int N>
-__device__ __forceinline__ void reconstruct_store64(const LatticeConst& L, const double (&ap)[Shape<Q1, N>::M],
+LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[Shape<Q1, N>::M],
                                                     float* __restrict__ out, long long stride, int node) {
   constexpr int p = Q1 / 2;
   constexpr int P2 = Shape<Q1, N>::P2;

@@ -33,7 +33,10 @@ struct lbsmrt_ctx {
   float* d_ghost = nullptr;
   double* d_ghost_fields = nullptr;
   int* d_err = nullptr;
-  double* d_partial = nullptr;   // [n_blocks][kTauCols] per-block partial sums
+  double* d_partial = nullptr;   // [n_blocks_adj][kTauCols] per-block partial sums
+  BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
+  double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
+  int n_blocks_adj = 0;
   int precision = LBSMRT_FP32;
 };
 
@@ -82,20 +85,24 @@ struct Launch {
   }
   static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
                       hipStream_t s) {
+    const size_t lds = 2 * sizeof(double) * n_moments(N) * 64;
     if (c->shock)
-      hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f_t, lam_next,
+      hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(c->n_blocks_adj), dim3(64), lds, s, c->L, A, f_t, lam_next,
                          lam_t, c->d_partial);
     else
-      hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f_t, lam_next,
+      hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), lds, s, c->L, A, f_t, lam_next,
                          lam_t, c->d_partial);
+    hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, c->n_blocks_adj,
+                       n_tau_slots(N), c->d_stage);
+    hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(64), 0, s, c->d_stage, kReduceBlocks, A.dtau);
   }
   static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
                         float* lam, hipStream_t s) {
     if (c->shock)
-      hipLaunchKernelGGL((k_loss_seed<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, target,
+      hipLaunchKernelGGL((k_loss_seed<Q1, N, true>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
                          c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
     else
-      hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, target,
+      hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
                          c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
   }
   static void equilibrium(lbsmrt_ctx* c, const double* fields, long long count, float* f, long long stride,
@@ -137,6 +144,8 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_ghost_fields);
   (void)hipFree(c->d_err);
   (void)hipFree(c->d_partial);
+  (void)hipFree(c->d_blocks_adj);
+  (void)hipFree(c->d_stage);
   delete c;
 }
 
@@ -269,6 +278,12 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
     for (long long first = 0; first < n; first += c->block) bl.push_back(BlockDev{i, static_cast<int>(first)});
   }
   c->n_blocks = static_cast<int>(bl.size());
+  std::vector<BlockDev> bla;
+  for (int i = 0; i < n_domains; ++i) {
+    const long long n = static_cast<long long>(domains[i].nx) * domains[i].ny * domains[i].nz;
+    for (long long first = 0; first < n; first += 64) bla.push_back(BlockDev{i, static_cast<int>(first)});
+  }
+  c->n_blocks_adj = static_cast<int>(bla.size());
   c->n_ghost = 2 * n_domains;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -279,8 +294,10 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (hipMalloc(&c->d_ghost, sizeof(float) * c->Q * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_ghost_fields, sizeof(double) * 5 * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess) return fail(LBSMRT_E_NOMEM);
-  if (hipMalloc(&c->d_partial, sizeof(double) * kTauCols * static_cast<size_t>(c->n_blocks)) != hipSuccess)
+  if (hipMalloc(&c->d_partial, sizeof(double) * kTauCols * static_cast<size_t>(c->n_blocks_adj)) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_blocks_adj, sizeof(BlockDev) * bla.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_stage, sizeof(double) * kTauCols * kReduceBlocks) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
   std::vector<double> gf(5 * c->n_ghost, 0.0);
   for (int i = 0; i < n_domains; ++i) {
@@ -297,6 +314,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   }
   if (hipMemcpyAsync(c->d_doms, dd.data(), sizeof(DomainDev) * dd.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(c->d_blocks, bl.data(), sizeof(BlockDev) * bl.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(c->d_blocks_adj, bla.data(), sizeof(BlockDev) * bla.size(), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
       hipMemcpyAsync(c->d_ghost_fields, gf.data(), sizeof(double) * gf.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       hipMemsetAsync(c->d_err, 0, sizeof(int), s) != hipSuccess)
@@ -372,9 +391,10 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* 
   if (!c || !f_t || !lam_next || !lam_t || !dL_dtau) return LBSMRT_E_ARG;
   if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const StepArgs A = step_args(c);
+  StepArgs A = step_args(c);
+  A.blocks = c->d_blocks_adj;
+  A.dtau = dL_dtau;
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, s); });
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, c->d_partial, c->n_blocks, kTauCols, dL_dtau, 1);
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 
@@ -382,9 +402,12 @@ lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* c, const float* f, const double* targ
                                double* loss, void* stream) {
   if (!c || !f || !target || !scales || !lam || !loss || lam == f) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const StepArgs A = step_args(c);
+  StepArgs A = step_args(c);
+  A.blocks = c->d_blocks_adj;
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::loss_seed(c, A, f, target, scales, lam, s); });
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, c->d_partial, c->n_blocks, 1, loss, 0);
+  hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, c->n_blocks_adj, 1,
+                     c->d_stage);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, c->d_stage, kReduceBlocks, 1, loss, 0);
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 

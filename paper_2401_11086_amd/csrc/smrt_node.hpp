@@ -10,6 +10,12 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+// The large per-node phases are force-inlined; defining LBSMRT_PHASE as
+// "__device__ __noinline__" gives per-phase register reports.
+#ifndef LBSMRT_PHASE
+#define LBSMRT_PHASE __device__ __forceinline__
+#endif
+
 namespace lbsmrt {
 
 constexpr int kMaxQ1 = 9;
