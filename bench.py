@@ -128,6 +128,62 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     return out
 
 
+def time_batched(torch, n_shocks=64, steps=5000, seed=0):
+    """Batched Mach sweep: n_shocks shocks with Ma ~ U[1.2, 5] and Nx ~ U{400..2000}, D3Q729
+    (D1Q9 degree 11), N = 5, FP32 state, `steps` steps, in one context with the autotuned launch,
+    against the same shocks stepped as separate contexts (one launch per shock per step)."""
+    from paper_2401_11086_amd import Lattice, solve_quadrature
+    from paper_2401_11086_amd import workloads as W
+    from paper_2401_11086_amd.autotune import autotune
+    from paper_2401_11086_amd.shocks import shock_domain
+    import numpy as np
+    ab, deg, N = [1, 2, 3, 5], 11, 5
+    c_l, _ = solve_quadrature(ab, deg)
+    draws = W.mach_sweep(n_shocks, seed=seed)
+    doms, fields = [], []
+    for Ma, nx in draws:
+        d, f, _ = shock_domain(Ma, nx, c_l)
+        doms.append(d)
+        fields.append(f)
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= N}
+    lat = Lattice(ab, deg, N, tau, doms, shift_k=(2, 0, 0), precision="fp64_contract")
+    fl = torch.tensor(np.concatenate(fields, axis=1), dtype=torch.float64, device="cuda")
+    fa = lat.equilibrium(fl)
+    fb = lat.new_state()
+    f0 = fa.clone()
+    tune = autotune(lat, fa, fb, steps=50, use_cache=False)
+    fa.copy_(f0)
+    ms = _time_steps(torch, lambda: lat.step(fa, fb, steps), 1) / steps
+    lat.sync()
+    nodes = lat.n_nodes
+    out = {"workload": f"{n_shocks} shocks, Ma~U[1.2,5], Nx~U{{400..2000}} (sum {nodes}), D3Q729, N=5, "
+                       f"{steps} steps", "nodes": nodes,
+           "batched": {"launch": {"mode": tune["mode"], "block": tune["block"]}, "ms_per_step": round(ms, 5),
+                       "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
+                       "achieved_GBs": round(8.0 * lat.Q * nodes / (ms / 1e3) / 1e9, 1)},
+           "autotune_trials": tune.get("trials")}
+    _progress(f"batched sweep: {ms * 1e3:.1f} us/step ({tune['mode']}, {tune['block']})")
+    # the same shocks as separate contexts, one launch per shock per step
+    sep = []
+    for d, f in zip(doms, fields):
+        one = Lattice(ab, deg, N, tau, [d], shift_k=(2, 0, 0), precision="fp64_contract")
+        ga = one.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda"))
+        sep.append((one, ga, one.new_state()))
+    torch.cuda.synchronize()
+
+    def run_sep():
+        for t in range(steps):
+            for one, ga, gb in sep:
+                one.step(ga, gb, 1) if t % 2 == 0 else one.step(gb, ga, 1)
+    ms_sep = _time_steps(torch, run_sep, 1) / steps
+    for one, _, _ in sep:
+        one.sync()
+    out["separate_contexts"] = {"ms_per_step": round(ms_sep, 5), "mlups": round(nodes / (ms_sep / 1e3) / 1e6, 1)}
+    out["speedup_batched_vs_separate"] = round(ms_sep / ms, 2)
+    _progress(f"separate contexts: {ms_sep * 1e3:.1f} us/step")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +193,8 @@ def main():
     ap.add_argument("--kn", type=float, default=0.05)
     ap.add_argument("--precision", default="fp64_contract", choices=["fp32", "fp64_contract"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-only", action="store_true", help="run only the batched Mach sweep")
+    ap.add_argument("--batched-steps", type=int, default=5000)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-contraction and adjoint timings")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -154,6 +212,9 @@ def main():
 
     ab, deg, N, edge = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.batched_only:
+        print(json.dumps({"batched_mach_sweep": time_batched(torch, steps=args.batched_steps)}), flush=True)
+        return
     if args.calibrate_copy:
         copy_calibration(torch, 343 * edge ** 3 if N == 4 else 729 * edge ** 3, args.steps, args.warmup)
         return
@@ -196,6 +257,7 @@ def main():
     variants = {}
     if not args.no_variants:
         variants = time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step)
+        variants["batched_mach_sweep"] = time_batched(torch, steps=args.batched_steps)
 
     out = {
         "metric": "MLUPS & % HBM/MFMA roofline, SMRT collide-stream; FP32 vs split-BF16; adjoint",

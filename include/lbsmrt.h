@@ -83,6 +83,8 @@ typedef struct {
   int    bc_x;
   double rho_in, u_in[3], theta_in;     /* lab-frame velocity */
   double rho_out, u_out[3], theta_out;
+  double tau_scale;                     /* multiplies every tau_nm in this domain (its own Knudsen
+                                           number); 0 means 1 */
 } lbsmrt_domain;
 
 /* Sizes of a context, filled by lbsmrt_get_info. */
@@ -108,6 +110,21 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
                                   int n_domains, void* stream, lbsmrt_ctx** out);
 
 lbsmrt_status lbsmrt_get_info(const lbsmrt_ctx* ctx, lbsmrt_info* out);
+
+/* How lbsmrt_step issues its work (lbsmrt_set_launch):
+ *  LBSMRT_LAUNCH_DIRECT      one kernel launch per step over all domains (default);
+ *  LBSMRT_LAUNCH_GRAPH       replays a captured hipGraph of `graph_steps` launches (even), captured on
+ *                            first use for a given (f_a, f_b) pair and recaptured when the pair, the
+ *                            launch settings or the relaxation times change;
+ *  LBSMRT_LAUNCH_PERSISTENT  one cooperative launch running all steps, work-groups resident and
+ *                            striding over the node blocks, a grid-wide barrier between steps. */
+enum { LBSMRT_LAUNCH_DIRECT = 0, LBSMRT_LAUNCH_GRAPH = 1, LBSMRT_LAUNCH_PERSISTENT = 2 };
+
+/* Choose the launch mode and the work-group size (64, 128 or 256; 0 keeps the current one).
+ * Results do not depend on either choice (each node's arithmetic is the same).  Synchronous.
+ * E_ARG for an unknown mode, size or odd graph_steps; E_UNSUPPORTED if the persistent kernel
+ * cannot be made resident. */
+lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* ctx, int mode, int block_size, int graph_steps);
 
 /* Advance n_steps >= 1 time steps (Sec. 3-4: stream, then SMRT collision).
  * Step t reads buffer A if t is even, B if odd, and writes the other one, so

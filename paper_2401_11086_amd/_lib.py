@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_HERE, "liblbsmrt.so")
 
 OK, E_ARG, E_QUADRATURE, E_STATE, E_HIP, E_NOMEM, E_UNSUPPORTED = range(7)
 FP32, SPLIT_BF16X3, FP64_CONTRACT = 0, 1, 2
+LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_PERSISTENT = 0, 1, 2
 MOM_BASIC, MOM_SIGMA, MOM_Q, MOM_M3, MOM_R41, MOM_R42, MOM_DLOCAL, MOM_ALAB = (1, 2, 4, 8, 16, 32, 64, 128)
 
 
@@ -36,6 +37,7 @@ class DomainDesc(ctypes.Structure):
         ("bc_x", ctypes.c_int),
         ("rho_in", ctypes.c_double), ("u_in", ctypes.c_double * 3), ("theta_in", ctypes.c_double),
         ("rho_out", ctypes.c_double), ("u_out", ctypes.c_double * 3), ("theta_out", ctypes.c_double),
+        ("tau_scale", ctypes.c_double),
     ]
 
 
@@ -78,6 +80,7 @@ _SIGS = {
                                         ctypes.c_void_p]),
     "lbsmrt_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "lbsmrt_set_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "lbsmrt_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbsmrt_destroy": (None, [ctypes.c_void_p]),
     "lbsmrt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lbsmrt_solve_quadrature": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,

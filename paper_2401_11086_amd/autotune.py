@@ -1,0 +1,72 @@
+"""Launch autotuner: picks lbsmrt_set_launch's mode and work-group size by timing
+a few steps of the caller's own lattice, and caches the choice in a JSON file
+keyed by device, velocity set, order, precision and problem-size bucket."""
+import json
+import math
+import os
+
+import torch
+
+CANDIDATES = [("direct", 64), ("direct", 128), ("direct", 256), ("graph", 64), ("graph", 128), ("graph", 256),
+              ("persistent", 64), ("persistent", 128), ("persistent", 256)]
+
+
+def _cache_path():
+    return os.environ.get("LBSMRT_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "lbsmrt", "autotune.json"))
+
+
+def _key(lat):
+    props = torch.cuda.get_device_properties(lat.device)
+    arch = getattr(props, "gcnArchName", props.name)
+    bucket = int(round(math.log2(max(lat.n_nodes, 1))))
+    return f"{arch}|Q{lat.Q}|N{lat.N}|{lat.precision}|nodes2^{bucket}|dom{len(lat.domains)}"
+
+
+def _time(lat, fa, fb, steps):
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat.step(fa, fb, 2)
+    torch.cuda.synchronize()
+    ev0.record()
+    lat.step(fa, fb, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    lat.sync()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def autotune(lat, fa, fb, steps=20, graph_steps=32, use_cache=True):
+    """Time every candidate on (fa, fb) (their contents are advanced), apply the fastest,
+    and return {'mode', 'block', 'ms_per_step', 'trials'}."""
+    path = _cache_path()
+    key = _key(lat)
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        best = cache[key]
+        lat.set_launch(best["mode"], best["block"], graph_steps)
+        return dict(best, cached=True)
+    trials = []
+    for mode, block in CANDIDATES:
+        try:
+            lat.set_launch(mode, block, graph_steps)
+        except Exception:
+            continue
+        trials.append((mode, block, _time(lat, fa, fb, steps)))
+    mode, block, ms = min(trials, key=lambda t: t[2])
+    lat.set_launch(mode, block, graph_steps)
+    best = {"mode": mode, "block": block, "ms_per_step": round(ms, 5)}
+    if use_cache:
+        cache[key] = best
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return dict(best, trials=[{"mode": m, "block": b, "ms": round(t, 5)} for m, b, t in trials], cached=False)

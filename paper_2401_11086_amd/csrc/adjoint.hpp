@@ -184,7 +184,7 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
   constexpr int M = n_moments(N);
   const double rho = mac.rho, th = mac.th;
   const double u[3] = {mac.ux, mac.uy, mac.uz};
-  const double sc = L.density_scaling ? L.rho_ref / rho : 1.0;
+  const double sc = mac.tsc * (L.density_scaling ? L.rho_ref / rho : 1.0);
   double ubar[3] = {0.0, 0.0, 0.0};
   double thbar = 0.0, rhobar = 0.0;
   const double sq = sqrt(th);
@@ -310,7 +310,7 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
       if (2 * m > n || (n == 2 && m == 1)) continue;
       const double w = om[m];
       tb[tau_slot(n, m)] += ob[m] * (-sc * w * w);
-      if (L.density_scaling) rhobar += ob[m] * (w * w * L.tau[n][m] * L.rho_ref / (rho * rho));
+      if (L.density_scaling) rhobar += ob[m] * (w * w * L.tau[n][m] * mac.tsc * L.rho_ref / (rho * rho));
     }
   }
 

@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void k_adjoint(LatticeConst L, StepArgs A, con
       gather_project64<Q1, N, SHOCK>(L, A, f_t, P, d);
       sums_from_a<N>(d, L, S);
       mac = macro_from_sums(L, S, A.err);
+      mac.tsc = P.tsc;
       to_local<N>(d, mac);
 #pragma unroll
       for (int i = 0; i < M; ++i) dv.set(i, d[i]);

@@ -7,6 +7,7 @@
 // Hermite tables held in scalar registers; the conserved sums, the frame
 // shift, the irreducible split and the relaxation run in FP64.
 #pragma once
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "smrt_node.hpp"
@@ -19,6 +20,7 @@ struct DomainDev {
   int bc_x;           // 0 periodic, 1 fixed Maxwellian ends
   int ghost;          // column of the left ghost state in the ghost table (right = ghost+1)
   int pad;
+  double tau_scale;   // multiplies every tau_nm of this domain
 };
 
 struct BlockDev {
@@ -63,11 +65,13 @@ struct Pull {
   unsigned yo[Q1];           // byte offset of source row ys*nx per iy
   unsigned zo[Q1];           // byte offset of source plane zs*nx*ny per iz
   int gcol;                  // left ghost column
+  double tsc;                // tau scale of the domain
 };
 
 template <int Q1>
-__device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs& A, Pull<Q1>& P) {
-  const BlockDev bd = A.blocks[blockIdx.x];
+__device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs& A, Pull<Q1>& P,
+                                          int work_block = -1) {
+  const BlockDev bd = A.blocks[work_block < 0 ? static_cast<int>(blockIdx.x) : work_block];
   const DomainDev D = A.doms[bd.dom];
   const int local = bd.first + static_cast<int>(threadIdx.x);
   const int nxy = D.nx * D.ny;
@@ -81,6 +85,7 @@ __device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs&
   P.nx = D.nx;
   P.bc_x = D.bc_x;
   P.gcol = D.ghost;
+  P.tsc = D.tau_scale;
 #pragma unroll
   for (int j = 0; j < Q1; ++j) {
     int t = (y - (L.e[j] + L.k[1])) % D.ny;
@@ -433,6 +438,7 @@ __device__ __forceinline__ void sums_from_a(const double* a, const LatticeConst&
 // Conserved moments -> rho, u' (relative to ubar), theta; validity (Sec. 4.1).
 struct Macro {
   double rho, ux, uy, uz, th;
+  double tsc = 1.0;   // tau scale of the node's domain
 };
 
 __device__ __forceinline__ Macro macro_from_sums(const LatticeConst& L, const double (&S)[5], int* err) {
@@ -481,8 +487,8 @@ __device__ __forceinline__ void to_lattice(double* d, const Macro& m) {
 
 // eq:SMRT with tau_nm(x) = tau_nm * (rho_ref / rho) [optional] and tau_bar = tau + offset.
 template <int N>
-__device__ __forceinline__ void relax(double* d, const LatticeConst& L, double rho) {
-  const double sc = L.density_scaling ? L.rho_ref / rho : 1.0;
+__device__ __forceinline__ void relax(double* d, const LatticeConst& L, double rho, double tsc) {
+  const double sc = tsc * (L.density_scaling ? L.rho_ref / rho : 1.0);
 #pragma unroll
   for (int n = 2; n <= N; ++n) {
     double om[3];
@@ -546,12 +552,14 @@ __device__ __forceinline__ void reconstruct_store(const LatticeConst& L, const f
 
 enum : int { kPrecFp32 = 0, kPrecFp64 = 2 };
 
+// One node of the fused step (work-block `wb` of the block table, or blockIdx.x when wb < 0).
 template <int Q1, int N, bool SHOCK, int PREC>
-__global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
-                                                        float* __restrict__ fdst) {
+__device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const StepArgs& A,
+                                                    const float* __restrict__ fsrc, float* __restrict__ fdst,
+                                                    int wb) {
   constexpr int M = Shape<Q1, N>::M;
   Pull<Q1> P;
-  if (!make_pull<Q1>(L, A, P)) return;
+  if (!make_pull<Q1>(L, A, P, wb)) return;
   double d[M];
   double S[5];
   if constexpr (PREC == kPrecFp64) {
@@ -567,9 +575,10 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs
     d[2] = L.r * S[2];
     d[3] = L.r * S[3];
   }
-  const Macro mac = macro_from_sums(L, S, A.err);
+  Macro mac = macro_from_sums(L, S, A.err);
+  mac.tsc = P.tsc;
   to_local<N>(d, mac);
-  relax<N>(d, L, mac.rho);
+  relax<N>(d, L, mac.rho, mac.tsc);
   to_lattice<N>(d, mac);
   if constexpr (PREC == kPrecFp64) {
     reconstruct_store64<Q1, N>(L, d, fdst, A.stride, P.node);
@@ -578,6 +587,28 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs
 #pragma unroll
     for (int i = 0; i < M; ++i) ap[i] = static_cast<float>(d[i]);
     reconstruct_store<Q1, N>(L, ap, fdst, A.stride, P.node);
+  }
+}
+
+template <int Q1, int N, bool SHOCK, int PREC>
+__global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
+                                                        float* __restrict__ fdst) {
+  collide_stream_node<Q1, N, SHOCK, PREC>(L, A, fsrc, fdst, -1);
+}
+
+// Persistent form: every work-group strides over the block table, n_steps times, with a grid-wide
+// barrier between steps (cooperative launch, so all work-groups are resident).  Step t reads
+// fa when t is even and fb when odd, as lbsmrt_step does.
+template <int Q1, int N, bool SHOCK, int PREC>
+__global__ __launch_bounds__(256) void k_collide_persistent(LatticeConst L, StepArgs A, float* fa, float* fb,
+                                                            int n_blocks, int n_steps) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int t = 0; t < n_steps; ++t) {
+    const float* src = (t & 1) ? fb : fa;
+    float* dst = (t & 1) ? fa : fb;
+    for (int wb = blockIdx.x; wb < n_blocks; wb += gridDim.x)
+      collide_stream_node<Q1, N, SHOCK, PREC>(L, A, src, dst, wb);
+    grid.sync();
   }
 }
 

@@ -1,6 +1,7 @@
 // C-ABI of the LB-SMRT library: context set-up, launches, error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -36,6 +37,13 @@ struct lbsmrt_ctx {
   double* d_partial = nullptr;   // [n_blocks_adj][kTauCols] per-block partial sums
   BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
   double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
+  // launch mode of lbsmrt_step
+  int mode = LBSMRT_LAUNCH_DIRECT;
+  int persistent_grid = 0;           // resident work-groups of the persistent kernel
+  hipGraphExec_t graph = nullptr;    // captured pair of steps for LBSMRT_LAUNCH_GRAPH
+  const float* graph_a = nullptr;
+  const float* graph_b = nullptr;
+  int graph_pairs = 0;
   int n_blocks_adj = 0;
   int precision = LBSMRT_FP32;
 };
@@ -74,6 +82,14 @@ struct Launch {
   static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
     if (c->precision == LBSMRT_FP32) step_p<kPrecFp32>(c, A, src, dst, s);
     else step_p<kPrecFp64>(c, A, src, dst, s);
+  }
+  template <int PREC, bool SH>
+  static const void* persistent_fn() {
+    return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC>);
+  }
+  static const void* persistent(const lbsmrt_ctx* c) {
+    if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
+    return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
   }
   static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s) {
     if (c->shock)
@@ -135,9 +151,16 @@ StepArgs step_args(const lbsmrt_ctx* c) {
   return A;
 }
 
+void drop_graph(lbsmrt_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_a = c->graph_b = nullptr;
+}
+
 void free_ctx(lbsmrt_ctx* c) {
   if (!c) return;
   if (c->device >= 0) (void)hipSetDevice(c->device);
+  drop_graph(c);
   (void)hipFree(c->d_doms);
   (void)hipFree(c->d_blocks);
   (void)hipFree(c->d_ghost);
@@ -147,6 +170,15 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_blocks_adj);
   (void)hipFree(c->d_stage);
   delete c;
+}
+
+std::vector<BlockDev> block_table(const std::vector<lbsmrt_domain>& doms, int bs) {
+  std::vector<BlockDev> bl;
+  for (size_t i = 0; i < doms.size(); ++i) {
+    const long long n = static_cast<long long>(doms[i].nx) * doms[i].ny * doms[i].nz;
+    for (long long first = 0; first < n; first += bs) bl.push_back(BlockDev{static_cast<int>(i), static_cast<int>(first)});
+  }
+  return bl;
 }
 
 lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
@@ -264,6 +296,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
     dd[i].bc_x = D.bc_x;
     dd[i].ghost = 2 * i;
     dd[i].pad = 0;
+    if (D.tau_scale < 0.0 || !std::isfinite(D.tau_scale)) { free_ctx(c); return LBSMRT_E_ARG; }
+    dd[i].tau_scale = D.tau_scale > 0.0 ? D.tau_scale : 1.0;
     c->dom_off.push_back(off);
     off += n;
     if (n > max_local) max_local = n;
@@ -272,17 +306,9 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (off >= (1LL << 30)) { free_ctx(c); return LBSMRT_E_ARG; }   // 32-bit node offsets in the kernels
   c->stride = (off + 63) / 64 * 64;
   c->block = (max_local >= 4096) ? 256 : 64;
-  std::vector<BlockDev> bl;
-  for (int i = 0; i < n_domains; ++i) {
-    const long long n = static_cast<long long>(domains[i].nx) * domains[i].ny * domains[i].nz;
-    for (long long first = 0; first < n; first += c->block) bl.push_back(BlockDev{i, static_cast<int>(first)});
-  }
+  std::vector<BlockDev> bl = block_table(c->doms, c->block);
   c->n_blocks = static_cast<int>(bl.size());
-  std::vector<BlockDev> bla;
-  for (int i = 0; i < n_domains; ++i) {
-    const long long n = static_cast<long long>(domains[i].nx) * domains[i].ny * domains[i].nz;
-    for (long long first = 0; first < n; first += 64) bla.push_back(BlockDev{i, static_cast<int>(first)});
-  }
+  std::vector<BlockDev> bla = block_table(c->doms, 64);
   c->n_blocks_adj = static_cast<int>(bla.size());
   c->n_ghost = 2 * n_domains;
 
@@ -345,12 +371,95 @@ lbsmrt_status lbsmrt_step(lbsmrt_ctx* c, float* f_a, float* f_b, int n_steps, vo
   if (!c || !f_a || !f_b || f_a == f_b || n_steps < 1) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const StepArgs A = step_args(c);
-  for (int t = 0; t < n_steps; ++t) {
-    const float* src = (t & 1) ? f_b : f_a;
-    float* dst = (t & 1) ? f_a : f_b;
-    dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::step(c, A, src, dst, s); });
+  auto direct = [&](int first_step, int count) {
+    for (int t = first_step; t < first_step + count; ++t) {
+      const float* src = (t & 1) ? f_b : f_a;
+      float* dst = (t & 1) ? f_a : f_b;
+      dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::step(c, A, src, dst, s); });
+    }
+  };
+  if (c->mode == LBSMRT_LAUNCH_PERSISTENT) {
+    const void* fn = nullptr;
+    dispatch(c->Q1, c->N, [&](auto l) { fn = decltype(l)::persistent(c); });
+    LatticeConst L = c->L;
+    StepArgs Ac = A;
+    float* fa = f_a;
+    float* fb = f_b;
+    int nb = c->n_blocks;
+    int ns = n_steps;
+    void* args[] = {&L, &Ac, &fa, &fb, &nb, &ns};
+    if (hipLaunchCooperativeKernel(fn, dim3(c->persistent_grid), dim3(c->block), args, 0, s) != hipSuccess)
+      return LBSMRT_E_HIP;
+    return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
   }
+  if (c->mode == LBSMRT_LAUNCH_GRAPH && n_steps >= 2 * c->graph_pairs) {
+    if (!c->graph || c->graph_a != f_a || c->graph_b != f_b) {
+      drop_graph(c);
+      hipStream_t cs = nullptr;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LBSMRT_E_HIP;
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        for (int t = 0; t < 2 * c->graph_pairs; ++t) {
+          const float* src = (t & 1) ? f_b : f_a;
+          float* dst = (t & 1) ? f_a : f_b;
+          dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::step(c, A, src, dst, cs); });
+        }
+        ok = hipStreamEndCapture(cs, &g) == hipSuccess;
+      }
+      if (ok) ok = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      if (!ok) { drop_graph(c); return LBSMRT_E_HIP; }
+      c->graph_a = f_a;
+      c->graph_b = f_b;
+    }
+    const int per = 2 * c->graph_pairs;
+    const int reps = n_steps / per;
+    for (int r = 0; r < reps; ++r)
+      if (hipGraphLaunch(c->graph, s) != hipSuccess) return LBSMRT_E_HIP;
+    direct(0, n_steps - reps * per);   // an even number of steps has returned the state to f_a
+    return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+  }
+  direct(0, n_steps);
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int graph_steps) {
+  if (!c) return LBSMRT_E_ARG;
+  if (mode != LBSMRT_LAUNCH_DIRECT && mode != LBSMRT_LAUNCH_GRAPH && mode != LBSMRT_LAUNCH_PERSISTENT)
+    return LBSMRT_E_ARG;
+  if (block_size != 0 && block_size != 64 && block_size != 128 && block_size != 256) return LBSMRT_E_ARG;
+  if (mode == LBSMRT_LAUNCH_GRAPH && (graph_steps < 2 || graph_steps > 4096 || (graph_steps & 1)))
+    return LBSMRT_E_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
+  drop_graph(c);
+  if (block_size != 0 && block_size != c->block) {
+    std::vector<BlockDev> bl = block_table(c->doms, block_size);
+    BlockDev* nb = nullptr;
+    if (hipMalloc(&nb, sizeof(BlockDev) * bl.size()) != hipSuccess) return LBSMRT_E_NOMEM;
+    if (hipMemcpy(nb, bl.data(), sizeof(BlockDev) * bl.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(nb);
+      return LBSMRT_E_HIP;
+    }
+    (void)hipFree(c->d_blocks);
+    c->d_blocks = nb;
+    c->n_blocks = static_cast<int>(bl.size());
+    c->block = block_size;
+  }
+  if (mode == LBSMRT_LAUNCH_PERSISTENT) {
+    const void* fn = nullptr;
+    dispatch(c->Q1, c->N, [&](auto l) { fn = decltype(l)::persistent(c); });
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, c->block, 0) != hipSuccess) return LBSMRT_E_HIP;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+      return LBSMRT_E_HIP;
+    if (per_cu < 1) return LBSMRT_E_UNSUPPORTED;
+    c->persistent_grid = std::min(c->n_blocks, per_cu * cus);
+  }
+  c->graph_pairs = mode == LBSMRT_LAUNCH_GRAPH ? graph_steps / 2 : 0;
+  c->mode = mode;
+  return LBSMRT_OK;
 }
 
 int lbsmrt_moment_rows(const lbsmrt_ctx* c, unsigned mask) {
@@ -422,6 +531,7 @@ lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* c, const double* tau) {
   for (int n = 2; n <= c->N; ++n)
     for (int m = 0; 2 * m <= n; ++m)
       if (!(n == 2 && m == 1)) c->L.tau[n][m] = tau[n * 3 + m];
+  drop_graph(c);   // captured launches hold the old relaxation times
   return LBSMRT_OK;
 }
 

@@ -54,6 +54,7 @@ class Lattice:
             x = arr[i]
             x.nx, x.ny, x.nz = int(dom["nx"]), int(dom.get("ny", 1)), int(dom.get("nz", 1))
             x.bc_x = int(dom.get("bc_x", 0))
+            x.tau_scale = float(dom.get("tau_scale", 1.0))
             if x.bc_x == 1:
                 x.rho_in, x.theta_in = float(dom["rho_in"]), float(dom["theta_in"])
                 x.rho_out, x.theta_out = float(dom["rho_out"]), float(dom["theta_out"])
@@ -61,6 +62,7 @@ class Lattice:
                     x.u_in[k] = float(dom["u_in"][k])
                     x.u_out[k] = float(dom["u_out"][k])
         self.domains = [dict(dm) for dm in domains]
+        self.precision = precision
         self.tau = dict(tau)
         self.shift_k = tuple(int(v) for v in shift_k)
         h = ctypes.c_void_p()
@@ -130,6 +132,12 @@ class Lattice:
             for m in range(3):
                 arr[n * 3 + m] = float(self.tau.get((n, m), 1.0))
         C.check(C.lib().lbsmrt_set_tau(self._h, arr), "lbsmrt_set_tau")
+
+    def set_launch(self, mode="direct", block_size=0, graph_steps=64):
+        """mode: 'direct', 'graph' or 'persistent' (see include/lbsmrt.h); block_size 64/128/256 or 0."""
+        m = {"direct": C.LAUNCH_DIRECT, "graph": C.LAUNCH_GRAPH, "persistent": C.LAUNCH_PERSISTENT}[mode]
+        C.check(C.lib().lbsmrt_set_launch(self._h, m, int(block_size), int(graph_steps)), "lbsmrt_set_launch")
+        self.launch = (mode, block_size, graph_steps)
 
     def sync(self):
         """Wait for the current stream; raise if a node left the validity region."""

@@ -1,0 +1,116 @@
+"""Batched shocks in one context: launch modes agree bitwise with each other and
+with separate per-shock contexts; graph replays are checked one by one."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_11086_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TAU_STAR = {k: float(v) for k, v in O.TAU_STAR_SMRT.items()}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _batch(torch, draws, ab=(1, 2, 3), deg=9, N=4, k=1):
+    from paper_2401_11086_amd import Lattice, solve_quadrature
+    from paper_2401_11086_amd.shocks import shock_domain
+    c_l, _ = solve_quadrature(list(ab), deg)
+    doms, fields = [], []
+    for Ma, nx in draws:
+        d, f, _ = shock_domain(Ma, nx, c_l)
+        doms.append(d)
+        fields.append(f)
+    tau = {key: v for key, v in TAU_STAR.items() if key[0] <= N}
+    lat = Lattice(list(ab), deg, N, tau, doms, shift_k=(k, 0, 0), precision="fp64_contract")
+    fl = torch.tensor(np.concatenate(fields, axis=1), dtype=torch.float64, device="cuda")
+    return lat, fl, doms, fields, tau
+
+
+DRAWS = [(1.2, 37), (1.6, 64), (2.2, 91), (1.35, 50), (2.0, 130)]
+
+
+def test_batched_equals_separate_contexts(torch):
+    from paper_2401_11086_amd import Lattice
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    fa = lat.equilibrium(fl)
+    fb = lat.new_state()
+    cur = lat.step(fa, fb, 20)
+    lat.sync()
+    for i, (d, f) in enumerate(zip(doms, fields)):
+        one = Lattice([1, 2, 3], 9, 4, tau, [d], shift_k=(1, 0, 0), precision="fp64_contract")
+        ga = one.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda"))
+        gb = one.new_state()
+        gc = one.step(ga, gb, 20)
+        one.sync()
+        off, n = lat.domain_offset[i], d["nx"]
+        assert torch.equal(cur[:, off:off + n], gc[:, :n]), i
+
+
+@pytest.mark.parametrize("mode", ["graph", "persistent"])
+def test_launch_modes_match_direct_bitwise(torch, mode):
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    f0 = lat.equilibrium(fl)
+    ref_a, ref_b = lat.new_state(), lat.new_state()
+    ref_a.copy_(f0)
+    ref = lat.step(ref_a, ref_b, 13)
+    lat.sync()
+    lat.set_launch(mode, 0, 4)
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    out = lat.step(fa, fb, 13)
+    lat.sync()
+    n = lat.n_nodes
+    assert torch.equal(out[:, :n], ref[:, :n])
+
+
+def test_graph_replays_each_match_eager(torch):
+    """Graph replays interleaved with eager work: every replay equals the eager result."""
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    f0 = lat.equilibrium(fl)
+    ea, eb = lat.new_state(), lat.new_state()
+    ea.copy_(f0)
+    ga, gb = lat.new_state(), lat.new_state()
+    ga.copy_(f0)
+    lat_g, _, _, _, _ = _batch(torch, DRAWS)
+    lat_g.set_launch("graph", 0, 4)
+    n = lat.n_nodes
+    for rep in range(5):
+        lat.step(ea, eb, 4)          # eager reference, 4 steps -> back in ea
+        lat_g.step(ga, gb, 4)        # one replay of the captured 4 steps
+        junk = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
+        lat.sync()
+        lat_g.sync()
+        assert torch.isfinite(junk)
+        assert torch.equal(ga[:, :n], ea[:, :n]), rep
+
+
+def test_batched_shock_matches_oracle_one_step(torch):
+    """tau_scale per domain: one step of a two-shock batch against the oracle, per shock."""
+    lat, fl, doms, fields, tau = _batch(torch, [(1.3, 40), (2.5, 60)])
+    fa = lat.equilibrium(fl)
+    n = lat.n_nodes
+    fa[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=9), dtype=torch.float32, device="cuda")
+    fb = lat.new_state()
+    lat.step(fa, fb, 1)
+    lat.sync()
+    vs = O.make_velocity_set([1, 2, 3], 9)
+    f0 = fa.cpu().numpy()
+    f1 = fb.cpu().numpy()
+    for i, d in enumerate(doms):
+        off, nx = lat.domain_offset[i], d["nx"]
+        model = O.Model(vs=vs, N=4, tau={k: v * d["tau_scale"] for k, v in tau.items()}, shift=(1, 0, 0))
+        dom = O.Domain(nx=nx, bc_x=1, state_in=(d["rho_in"], d["u_in"], d["theta_in"]),
+                       state_out=(d["rho_out"], d["u_out"], d["theta_out"]))
+        fo = O.step(f0[:, off:off + nx].astype(np.float64).reshape(-1, 1, 1, nx), model, dom)
+        g = f1[:, off:off + nx].reshape(fo.shape)
+        assert np.abs(g - fo).max() / np.abs(fo).max() < 1e-5, i
