@@ -253,3 +253,68 @@ def test_box_conserves_mass_momentum_energy(torch, precision):
     # FP32 contractions carry the float32 rounding of the rebuild tables (~2e-8 relative per step)
     bound = 2e-7 if precision == "fp64_contract" else 2e-5
     assert max(drift) < bound, drift
+
+
+@pytest.mark.parametrize("preset", ["shakhov", "bgk", "lumped", "reduced"])
+def test_relaxation_presets_one_step_match_oracle(torch, preset):
+    """Table 4's Shakhov column, BGK, one tau per order and the reduced n=4 variant."""
+    from paper_2401_11086_amd.presets import PRESETS
+    table = {k: v for k, v in PRESETS[preset].items()}
+    table[(2, 1)] = table[(2, 0)]
+    case = shock_case(3.0, 30, D1Q9, 5, table=table)
+    lat = _lattice(case, "fp64_contract")
+    f0 = _gpu_state(torch, lat, case, noise_seed=2)
+    fo0 = oracle_state_from_gpu(_host(f0), case)
+    f1 = lat.new_state()
+    lat.step(f0, f1, 1)
+    lat.sync()
+    fo1 = O.step(fo0, case["model"], case["dom"])
+    g = _host(f1)[:, :30].reshape(fo1.shape)
+    assert np.abs(g - fo1).max() / np.abs(fo1).max() < TOL_STEP
+
+
+def test_d3q729_shock_trajectory_matches_oracle(torch):
+    """Ma = 3, D3Q729, N = 5, 40 cells, 600 steps: aligned normalised profiles within 1e-4."""
+    from paper_2401_11086_amd import _lib as C
+    case = shock_case(3.0, 40, D1Q9, 5)
+    lat = _lattice(case, "fp64_contract")
+    fa = _gpu_state(torch, lat, case)
+    fb = lat.new_state()
+    fo = oracle_state_from_gpu(_host(fa), case)
+    st = case["states"]
+    for seg in range(3):
+        cur = lat.step(fa, fb, 200)
+        if cur is fb:
+            fa, fb = fb, fa
+        lat.sync()
+        for _ in range(200):
+            fo = O.step(fo, case["model"], case["dom"])
+        g = _gpu_moments(lat, fa, C.MOM_BASIC | C.MOM_Q)
+        ob = O.observables(fo, case["model"], case["dom"])
+        gn = _normalised(g[0], g[4], g[5], st)
+        on = _normalised(ob["rho"], ob["theta"], ob["q"][0], st)
+        raw = max(float(np.abs(a - b).max()) for a, b in zip(gn, on))
+        print(f"step {200 * (seg + 1)}: raw normalised-profile difference {raw:.2e}")
+        assert raw < TOL_PROFILE, (seg, raw)
+
+
+def test_steady_state_driver_reaches_rankine_hugoniot_plateaus(torch):
+    """Ma = 1.5 on D3Q343 to a steady state: end plateaus at the RH states, constant mass flux."""
+    from paper_2401_11086_amd import Lattice, _lib as C
+    from paper_2401_11086_amd.presets import tau_table
+    from paper_2401_11086_amd.shocks import shock_domain
+    from paper_2401_11086_amd.steady import run_to_steady
+    c_l = O.make_velocity_set([1, 2, 3], 9).r
+    dom, fields, st = shock_domain(1.5, 160, c_l, theta2=1.07)
+    k = O.shift_integer(0.5 * (st["u1"] + st["u2"]), c_l)
+    lat = Lattice([1, 2, 3], 9, 4, tau_table("smrt", 1.0, 4), [dom], shift_k=(k, 0, 0), precision="fp64_contract")
+    fa = lat.equilibrium(torch.tensor(fields, dtype=torch.float64, device="cuda"))
+    fb = lat.new_state()
+    res, f = run_to_steady(lat, fa, fb, max_steps=60000)
+    print(res)
+    assert res["converged"], res
+    m = lat.moments(f, C.MOM_BASIC).cpu().numpy()
+    assert abs(m[0][0] - 1.0) < 1e-2 and abs(m[0][-1] - st["rho2"]) < 1e-2
+    assert abs(m[4][0] - st["theta1"]) < 1e-2 and abs(m[4][-1] - st["theta2"]) < 1e-2
+    flux = m[0] * m[1]
+    assert np.abs(flux - flux.mean()).max() < 2e-3 * flux.mean()
