@@ -264,6 +264,42 @@ __device__ __forceinline__ void fold_slab_project(const LatticeConst& L, const f
   }
 }
 
+// As fold_slab_project, with the populations of each z line fetched just before it is folded
+// (load(iy, line) fills line[iz]); keeps at most two lines of a slab in registers.
+template <int Q1, int N, bool RW, class LineLoad>
+__device__ __forceinline__ void fold_slab_project_lines(const LatticeConst& L, const LineLoad& load,
+                                                        double (&t2)[n_sym(N)]) {
+  constexpr int p = Q1 / 2;
+  {
+    float g[Q1];
+    load(p, g);
+    double tc[N + 1];
+    fold_line_project<Q1, N, RW>(L, g, tc);
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az)
+        if (ay + az <= N) t2[pair_pos(ay, az)] = (ay & 1) ? 0.0 : tab_center<RW>(L, p, ay) * tc[az];
+  }
+#pragma unroll
+  for (int j = 1; j <= p; ++j) {
+    float gp[Q1], gm[Q1];
+    load(p + j, gp);
+    load(p - j, gm);
+    double tp[N + 1], tm[N + 1];
+    fold_line_project<Q1, N, RW>(L, gp, tp);
+    fold_line_project<Q1, N, RW>(L, gm, tm);
+#pragma unroll
+    for (int az = 0; az <= N; ++az) {
+      const double Pz = tp[az] + tm[az];
+      const double Mz = tp[az] - tm[az];
+#pragma unroll
+      for (int ay = 0; ay <= N; ++ay)
+        if (ay + az <= N) t2[pair_pos(ay, az)] = fma(tab<RW>(L, p + j, ay), (ay & 1) ? Mz : Pz, t2[pair_pos(ay, az)]);
+    }
+  }
+}
+
 // FP64 projection of a node's own populations (no streaming) with table T:
 //   out[ax,ay,az] = sum_{ix,iy,iz} T_ax(c_ix) T_ay(c_iy) T_az(c_iz) v[q]
 template <int Q1, int N, bool RW>
@@ -307,27 +343,27 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
   for (int ix = 0; ix < Q1; ++ix) {
     const int xs = source_x<Q1>(L, P, ix);
     const float* __restrict__ fx = f + static_cast<size_t>(ix * Q1 * Q1) * A.stride;
-    const unsigned xoff = static_cast<unsigned>(P.row + xs) * 4u;
-    float gs[Q1 * Q1];
-#pragma unroll
-    for (int iy = 0; iy < Q1; ++iy) {
+    // shock ends: every lane loads from an in-domain address; lanes whose source is a ghost
+    // cell then take the ghost value, on a path only waves that touch an end execute
+    const bool ghost = SHOCK && xs < 0;
+    const unsigned xoff = static_cast<unsigned>(P.row + (ghost ? 0 : xs)) * 4u;
+    const bool any_ghost = SHOCK && __any(ghost);
+    const float* __restrict__ gcol = A.ghosts + P.gcol + (xs == -2 ? 1 : 0);
+    auto load = [&](int iy, float (&line)[Q1]) {
       const unsigned xyoff = xoff + P.yo[iy];
 #pragma unroll
-      for (int iz = 0; iz < Q1; ++iz) {
-        const int qs = iy * Q1 + iz;
-        if constexpr (SHOCK) {
-          if (xs >= 0) {
-            gs[qs] = load_at(fx + static_cast<size_t>(qs) * A.stride, xyoff + P.zo[iz]);
-          } else {
-            gs[qs] = A.ghosts[static_cast<size_t>(ix * Q1 * Q1 + qs) * A.n_ghost + P.gcol + (xs == -1 ? 0 : 1)];
-          }
-        } else {
-          gs[qs] = load_at(fx + static_cast<size_t>(qs) * A.stride, xyoff + P.zo[iz]);
+      for (int iz = 0; iz < Q1; ++iz)
+        line[iz] = load_at(fx + static_cast<size_t>(iy * Q1 + iz) * A.stride, xyoff + P.zo[iz]);
+      if (any_ghost) {
+#pragma unroll
+        for (int iz = 0; iz < Q1; ++iz) {
+          const float gv = gcol[static_cast<size_t>(ix * Q1 * Q1 + iy * Q1 + iz) * A.n_ghost];
+          line[iz] = ghost ? gv : line[iz];
         }
       }
-    }
+    };
     double t2[P2];
-    fold_slab_project<Q1, N>(L, gs, t2);
+    fold_slab_project_lines<Q1, N, false>(L, load, t2);
     double hx[N + 1];
 #pragma unroll
     for (int n = 0; n <= N; ++n) hx[n] = L.He64[ix][n];
@@ -591,7 +627,7 @@ __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const
 }
 
 template <int Q1, int N, bool SHOCK, int PREC>
-__global__ __launch_bounds__(256) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
                                                         float* __restrict__ fdst) {
   collide_stream_node<Q1, N, SHOCK, PREC>(L, A, fsrc, fdst, -1);
 }

@@ -157,29 +157,47 @@ __device__ __forceinline__ void irreducible_piece(const double* dn, double* P) {
   }
 }
 
+// D = a D - delta Y  (rank L -> rank L+2, in place on D), the element-wise form of sym_delta
+template <int L>
+__device__ __forceinline__ void sym_delta_update(const double* Y, double a, double* D) {
+  constexpr double inv = 1.0 / binom(L + 2, 2);
+#pragma unroll
+  for (int x = 0; x <= L + 2; ++x)
+#pragma unroll
+    for (int y = 0; y <= L + 2; ++y) {
+      if (x + y > L + 2) continue;
+      const int z = L + 2 - x - y;
+      double s = 0.0;
+      if (x >= 2) s += binom(x, 2) * Y[sym_pos(L, x - 2, y)];
+      if (y >= 2) s += binom(y, 2) * Y[sym_pos(L, x, y - 2)];
+      if (z >= 2) s += binom(z, 2) * Y[sym_pos(L, x, y)];
+      D[sym_pos(L + 2, x, y)] = fma(a, D[sym_pos(L + 2, x, y)], -s * inv);
+    }
+}
+
 // eq:SMRT on order n: d'^(n) = sum_m (1 - om_m) d^(n,m) delta^m
-//                           = (1 - om_0) d^(n) - sum_{m>=1} (om_m - om_0) piece_m
+//   = (1 - om_0) d^(n) - sum_{m>=1} (om_m - om_0) sym(d^(n,m) delta^m)
+//   = (1 - om_0) d^(n) - delta [ (om_1 - om_0) d^(n,1) + (om_2 - om_0) delta d^(n,2) ]
+// (delta is linear), so only the rank n-2 bracket is held beside d^(n).
 template <int n>
 __device__ __forceinline__ void relax_order(double* dn, const double* om) {
-  double acc[n_sym(n)];
+  double Y[n_sym(n - 2)];
+  irreducible_part<n, 1>(dn, Y);
+  const double c1 = om[1] - om[0];
 #pragma unroll
-  for (int i = 0; i < n_sym(n); ++i) acc[i] = (1.0 - om[0]) * dn[i];
-  if constexpr (n >= 2) {
-    double P[n_sym(n)];
-    irreducible_piece<n, 1>(dn, P);
-    const double c1 = om[1] - om[0];
-#pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) acc[i] -= c1 * P[i];
-  }
+  for (int i = 0; i < n_sym(n - 2); ++i) Y[i] *= c1;
   if constexpr (n >= 4) {
-    double P[n_sym(n)];
-    irreducible_piece<n, 2>(dn, P);
+    double part[n_sym(n - 4)];
+    irreducible_part<n, 2>(dn, part);
     const double c2 = om[2] - om[0];
 #pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) acc[i] -= c2 * P[i];
-  }
+    for (int i = 0; i < n_sym(n - 4); ++i) part[i] *= c2;
+    double dp[n_sym(n - 2)];
+    sym_delta<n - 4>(part, dp);
 #pragma unroll
-  for (int i = 0; i < n_sym(n); ++i) dn[i] = acc[i];
+    for (int i = 0; i < n_sym(n - 2); ++i) Y[i] += dp[i];
+  }
+  sym_delta_update<n - 2>(Y, 1.0 - om[0], dn);
 }
 
 // ------------------------------------------------------------------ frame shift
