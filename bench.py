@@ -37,6 +37,37 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_collide_stream_box256_q343_n4.md")
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources and the C header, in a fixed order: the key under which
+    the HBM traffic counters of the step kernel were recorded."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2401_11086_amd", "csrc")
+    files = sorted(os.path.join(csrc, n) for n in os.listdir(csrc) if n.endswith((".hpp", ".hip", ".cpp")))
+    for path in files + [os.path.join(ROOT, "include", "lbsmrt.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per launch of the step kernel from the committed FETCH_SIZE / WRITE_SIZE counter
+    summary, if it was taken on this workload and precision with the current sources; else None."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(ln[2:].split(": ", 1) for ln in fh.read().splitlines() if ln.startswith("- ") and ": " in ln)
+        if (kv.get("workload") != workload or kv.get("precision") != precision
+                or kv.get("source_sha256") != kernel_source_digest()):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(ab, deg, N, edge, kn, sample_edge=32, steps=12):
     """The FP64 oracle on a sample_edge^3 box of the same Fourier workload
     (same modes), `steps` steps; MLUPS scaled from that sample."""
@@ -278,7 +309,8 @@ def main():
                                   else "FP32 contractions") + ", FP64 moment section",
                    "nodes": nodes, "Q": lat.Q, "M": lat.M, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(args.workload, args.precision),
                      "kernel": f"k_collide_stream<{lat.Q1},{N}>", "bytes_per_launch": bytes_per_launch},
     }
     if variants:
