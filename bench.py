@@ -159,6 +159,33 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     return out
 
 
+def time_shock_adjoint(torch, steps=300):
+    """The adjoint-calibration shock (Ma 3, Nx 600, D3Q729, N = 5, FP64 contractions): forward and
+    adjoint step times on one small domain, where each wave's latency, not HBM, sets the time."""
+    from paper_2401_11086_amd import Lattice, solve_quadrature
+    from paper_2401_11086_amd.shocks import shock_domain
+    ab, deg, N = [1, 2, 3, 5], 11, 5
+    c_l, _ = solve_quadrature(ab, deg)
+    d, f, _ = shock_domain(3.0, 600, c_l)
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= N}
+    lat = Lattice(ab, deg, N, tau, [d], shift_k=(2, 0, 0), precision="fp64_contract")
+    fa = lat.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda"))
+    fb = lat.new_state()
+    lat.step(fa, fb, 10)
+    ms_fwd = _time_steps(torch, lambda: lat.step(fa, fb, 1), steps)
+    lam_a, lam_b = lat.new_state(), lat.new_state()
+    lam_a.normal_()
+    dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
+    lat.step_adjoint(fa, lam_a, lam_b, dtau)
+    ms_adj = _time_steps(torch, lambda: lat.step_adjoint(fa, lam_a, lam_b, dtau), steps)
+    lat.sync()
+    assert torch.isfinite(dtau).all()
+    lat.close()
+    _progress(f"shock adjoint (Nx 600, D3Q729): forward {ms_fwd * 1e3:.1f} us, adjoint {ms_adj * 1e3:.1f} us")
+    return {"workload": "Ma 3 shock, Nx 600, D3Q729, N=5, FP64 contractions", "forward_us": round(ms_fwd * 1e3, 2),
+            "adjoint_us": round(ms_adj * 1e3, 2), "ratio_to_forward": round(ms_adj / ms_fwd, 3)}
+
+
 def time_batched(torch, n_shocks=64, steps=5000, seed=0):
     """Batched Mach sweep: n_shocks shocks with Ma ~ U[1.2, 5] and Nx ~ U{400..2000}, D3Q729
     (D1Q9 degree 11), N = 5, FP32 state, `steps` steps, in one context with the autotuned launch,
@@ -288,6 +315,7 @@ def main():
     variants = {}
     if not args.no_variants:
         variants = time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step)
+        variants["shock_adjoint"] = time_shock_adjoint(torch)
         variants["batched_mach_sweep"] = time_batched(torch, steps=args.batched_steps)
 
     out = {

@@ -16,125 +16,6 @@
 
 namespace lbsmrt {
 
-// ---------------------------------------------------------------- transposed tensor operators
-// transpose of sym_trace<L>: rank L -> rank L+2
-template <int L>
-__device__ __forceinline__ void sym_trace_T(const double* Tb, double* Xb) {
-#pragma unroll
-  for (int i = 0; i < n_sym(L + 2); ++i) Xb[i] = 0.0;
-#pragma unroll
-  for (int a = 0; a <= L; ++a)
-#pragma unroll
-    for (int b = 0; b <= L; ++b)
-      if (a + b <= L) {
-        const double t = Tb[sym_pos(L, a, b)];
-        Xb[sym_pos(L + 2, a + 2, b)] += t;
-        Xb[sym_pos(L + 2, a, b + 2)] += t;
-        Xb[sym_pos(L + 2, a, b)] += t;
-      }
-}
-
-// transpose of sym_delta<L>: rank L+2 -> rank L
-template <int L>
-__device__ __forceinline__ void sym_delta_T(const double* Pb, double* Yb) {
-  constexpr double inv = 1.0 / binom(L + 2, 2);
-#pragma unroll
-  for (int i = 0; i < n_sym(L); ++i) Yb[i] = 0.0;
-#pragma unroll
-  for (int a = 0; a <= L + 2; ++a)
-#pragma unroll
-    for (int b = 0; b <= L + 2; ++b) {
-      if (a + b > L + 2) continue;
-      const int c = L + 2 - a - b;
-      const double p = Pb[sym_pos(L + 2, a, b)] * inv;
-      if (a >= 2) Yb[sym_pos(L, a - 2, b)] += binom(a, 2) * p;
-      if (b >= 2) Yb[sym_pos(L, a, b - 2)] += binom(b, 2) * p;
-      if (c >= 2) Yb[sym_pos(L, a, b)] += binom(c, 2) * p;
-    }
-}
-
-// transpose of traceless<L>: Y' = Y + D(L,1) delta tr Y  ->  Yb += D(L,1) tr^T delta^T Yb'
-template <int L>
-__device__ __forceinline__ void traceless_T(double* Yb) {
-  if constexpr (L >= 2) {
-    double t[n_sym(L - 2)];
-    double x[n_sym(L)];
-    sym_delta_T<L - 2>(Yb, t);
-    sym_trace_T<L - 2>(t, x);
-    constexpr double dk = coefD(L, 1);
-#pragma unroll
-    for (int i = 0; i < n_sym(L); ++i) Yb[i] += dk * x[i];
-  }
-}
-
-// transpose of irreducible_piece<n,m> (m >= 1): rank n -> rank n
-template <int n, int m>
-__device__ __forceinline__ void irreducible_piece_T(const double* Pb, double* Db) {
-  constexpr int L = n - 2 * m;
-  double part[n_sym(L)];
-  if constexpr (m == 1) {
-    sym_delta_T<L>(Pb, part);
-  } else {
-    double tmp[n_sym(L + 2)];
-    sym_delta_T<L + 2>(Pb, tmp);
-    sym_delta_T<L>(tmp, part);
-  }
-  constexpr double bnm = coefB(n, m);
-#pragma unroll
-  for (int i = 0; i < n_sym(L); ++i) part[i] *= bnm;
-  traceless_T<L>(part);
-  if constexpr (m == 1) {
-    sym_trace_T<L>(part, Db);
-  } else {
-    double t1[n_sym(n - 2)];
-    sym_trace_T<L>(part, t1);
-    sym_trace_T<n - 2>(t1, Db);
-  }
-}
-
-template <int n>
-__device__ __forceinline__ double dotn(const double* x, const double* y) {
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < n_sym(n); ++i) s = fma(x[i], y[i], s);
-  return s;
-}
-
-// Adjoint of relax_order<n>: in dpb = dL/dd'^(n), dn = d^(n) (forward input);
-// out dpb <- dL/dd^(n); ob[m] += dL/domega_nm.
-template <int n>
-__device__ __forceinline__ void relax_order_T(double* dpb, const double* dn, const double* om, double* ob) {
-  double acc[n_sym(n)];
-#pragma unroll
-  for (int i = 0; i < n_sym(n); ++i) acc[i] = (1.0 - om[0]) * dpb[i];
-  double rest = dotn<n>(dpb, dn);  // d'.d  -> becomes d'.P_0 d after removing the pieces
-  {
-    double P[n_sym(n)], PT[n_sym(n)];
-    irreducible_piece<n, 1>(dn, P);
-    const double s1 = dotn<n>(dpb, P);
-    ob[1] += -s1;
-    rest -= s1;
-    irreducible_piece_T<n, 1>(dpb, PT);
-    const double c1 = om[1] - om[0];
-#pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) acc[i] -= c1 * PT[i];
-  }
-  if constexpr (n >= 4) {
-    double P[n_sym(n)], PT[n_sym(n)];
-    irreducible_piece<n, 2>(dn, P);
-    const double s2 = dotn<n>(dpb, P);
-    ob[2] += -s2;
-    rest -= s2;
-    irreducible_piece_T<n, 2>(dpb, PT);
-    const double c2 = om[2] - om[0];
-#pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) acc[i] -= c2 * PT[i];
-  }
-  ob[0] += -rest;
-#pragma unroll
-  for (int i = 0; i < n_sym(n); ++i) dpb[i] = acc[i];
-}
-
 // Transpose of axis_transform<N,AXIS>:  xb_g = sum_{b >= g} C(b, g) P_{b-g} yb_b  (in place, bottom-up)
 template <int N, int AXIS>
 __device__ __forceinline__ void axis_transform_T(double* d, const double (&P)[N + 1]) {
@@ -198,6 +79,9 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     if (n == 2) om[1] = 0.0;   // the (2,1) part is left unrelaxed (it is zero)
   };
 
+  // The workgroup fences between phases make the compiler re-read d and z from LDS after each
+  // fence instead of keeping the values of an earlier phase live in registers.
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   // ---- z = Lambda d' = Lambda K d, into LDS
   zv.set(0, dv(0));
   zv.set(1, 0.0);
@@ -218,6 +102,7 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     for (int i = 0; i < n_sym(n); ++i) zv.set(order_start(n) + i, t[i] * sp[n]);
   }
 
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   // ---- a' = T_A z  (reverse): zbar = T_A^T abar; u, theta sensitivities in z space
   {
     double Ax[N + 1], Ay[N + 1], Az[N + 1];
@@ -229,6 +114,7 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     axis_transform_T<N, 0>(ab, Ax);
   }
   {
+    // each z_j is read once and feeds the components j + e_k and j + 2 e_k of abar
     const double i2th = 0.5 / th;
 #pragma unroll
     for (int a = 0; a <= N; ++a)
@@ -236,20 +122,22 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     for (int b = 0; b <= N; ++b)
 #pragma unroll
     for (int c = 0; c <= N; ++c) {
-      const int n = a + b + c;
-      if (n == 0 || n > N) continue;
-      const int i = midx(a, b, c);
-      const double g = ab[i];
-      if (a >= 1) ubar[0] += g * a * zv(midx(a - 1, b, c));
-      if (b >= 1) ubar[1] += g * b * zv(midx(a, b - 1, c));
-      if (c >= 1) ubar[2] += g * c * zv(midx(a, b, c - 1));
-      double t = (n * i2th) * zv(i);
-      if (a >= 2) t += binom(a, 2) * zv(midx(a - 2, b, c));
-      if (b >= 2) t += binom(b, 2) * zv(midx(a, b - 2, c));
-      if (c >= 2) t += binom(c, 2) * zv(midx(a, b, c - 2));
-      thbar += g * t;
+      const int m = a + b + c;
+      if (m > N) continue;
+      const double zj = zv(midx(a, b, c));
+      if (m + 1 <= N) {
+        ubar[0] += ab[midx(a + 1, b, c)] * (a + 1) * zj;
+        ubar[1] += ab[midx(a, b + 1, c)] * (b + 1) * zj;
+        ubar[2] += ab[midx(a, b, c + 1)] * (c + 1) * zj;
+      }
+      double t = (m >= 1) ? ab[midx(a, b, c)] * (m * i2th) : 0.0;
+      if (m + 2 <= N)
+        t += binom(a + 2, 2) * ab[midx(a + 2, b, c)] + binom(b + 2, 2) * ab[midx(a, b + 2, c)] +
+             binom(c + 2, 2) * ab[midx(a, b, c + 2)];
+      thbar += t * zj;
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   // d'bar = Lambda zbar; orders 0 and 1 of d' are rho and 0
 #pragma unroll
   for (int n = 2; n <= N; ++n)
@@ -258,53 +146,52 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
   rhobar += ab[0];
   ab[0] = ab[1] = ab[2] = ab[3] = 0.0;
 
-  // ---- relaxation (reverse):  dbar = W K W^{-1} d'bar,  omega_bar_m = -<P_m y, d>_W with y = W^{-1} d'bar
+  // ---- relaxation (reverse):  dbar = W K W^{-1} d'bar,  omega_bar_m = -<P_m y, d>_W with y = W^{-1} d'bar.
+  // With P_m y = delta^m part_m(y) and delta linear, K y = (1 - om_0) y - delta Y for the rank n-2
+  // bracket Y = (om_1 - om_0) part_1(y) + (om_2 - om_0) delta part_2(y); the components of
+  // delta part_1(y) and delta delta part_2(y) are formed one at a time.
 #pragma unroll
   for (int n = 2; n <= N; ++n) {
     double om[3];
     omegas(n, om);
-    constexpr int S = n_sym(kMaxN);
-    double y[S], wgt[S];
+    double* y = ab + order_start(n);
 #pragma unroll
     for (int a = 0; a <= n; ++a)
 #pragma unroll
       for (int b = 0; b <= n; ++b)
-        if (a + b <= n) wgt[sym_pos(n, a, b)] = multiplicity(a, b, n - a - b);
-#pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) y[i] = ab[order_start(n) + i] / wgt[i];
-    double ob[3] = {0.0, 0.0, 0.0};
-    double r[S];
-#pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) r[i] = (1.0 - om[0]) * y[i];
-    double p0d = 0.0;   // <y, d>_W
-#pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) p0d += wgt[i] * y[i] * dv(order_start(n) + i);
-#pragma unroll
-    for (int m = 1; m <= 2; ++m) {
-      if (2 * m > n) continue;
-      double P[S];
-      if (n == 2 && m == 1) irreducible_piece<2, 1>(y, P);
-      if (n == 3 && m == 1) irreducible_piece<3, 1>(y, P);
-      if constexpr (N >= 4) {
-        if (n == 4 && m == 1) irreducible_piece<4, 1>(y, P);
-        if (n == 4 && m == 2) irreducible_piece<4, 2>(y, P);
-      }
-      if constexpr (N >= 5) {
-        if (n == 5 && m == 1) irreducible_piece<5, 1>(y, P);
-        if (n == 5 && m == 2) irreducible_piece<5, 2>(y, P);
-      }
-      double pd = 0.0;
-#pragma unroll
-      for (int i = 0; i < n_sym(n); ++i) pd += wgt[i] * P[i] * dv(order_start(n) + i);
-      ob[m] = -pd;
-      p0d -= pd;
-      const double cm = om[m] - om[0];
-#pragma unroll
-      for (int i = 0; i < n_sym(n); ++i) r[i] -= cm * P[i];
+        if (a + b <= n) y[sym_pos(n, a, b)] *= 1.0 / multiplicity(a, b, n - a - b);
+    constexpr int S2 = n_sym(kMaxN - 2);
+    double Y1[S2], Y2[S2];
+    if (n == 2) irreducible_part<2, 1>(y, Y1);
+    if (n == 3) irreducible_part<3, 1>(y, Y1);
+    if constexpr (N >= 4) if (n == 4) irreducible_part<4, 1>(y, Y1);
+    if constexpr (N >= 5) if (n == 5) irreducible_part<5, 1>(y, Y1);
+    if (n >= 4) {
+      double p2[n_sym(kMaxN - 4)];
+      if constexpr (N >= 4) if (n == 4) { irreducible_part<4, 2>(y, p2); sym_delta<0>(p2, Y2); }
+      if constexpr (N >= 5) if (n == 5) { irreducible_part<5, 2>(y, p2); sym_delta<1>(p2, Y2); }
     }
-    ob[0] = -p0d;
+    const double c1 = om[1] - om[0], c2 = om[2] - om[0];
+    double p0d = 0.0, pd1 = 0.0, pd2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < n_sym(n); ++i) ab[order_start(n) + i] = r[i] * wgt[i];
+    for (int a = 0; a <= n; ++a)
+#pragma unroll
+      for (int b = 0; b <= n; ++b) {
+        if (a + b > n) continue;
+        const int i = sym_pos(n, a, b);
+        const double w = multiplicity(a, b, n - a - b);
+        const double di = dv(order_start(n) + i);
+        double q1 = 0.0, q2 = 0.0;
+        if (n == 2) q1 = sym_delta_at<0>(Y1, a, b);
+        if (n == 3) q1 = sym_delta_at<1>(Y1, a, b);
+        if constexpr (N >= 4) if (n == 4) { q1 = sym_delta_at<2>(Y1, a, b); q2 = sym_delta_at<2>(Y2, a, b); }
+        if constexpr (N >= 5) if (n == 5) { q1 = sym_delta_at<3>(Y1, a, b); q2 = sym_delta_at<3>(Y2, a, b); }
+        p0d += w * y[i] * di;
+        pd1 += w * q1 * di;
+        pd2 += w * q2 * di;
+        y[i] = ((1.0 - om[0]) * y[i] - c1 * q1 - c2 * q2) * w;
+      }
+    const double ob[3] = {-(p0d - pd1 - pd2), -pd1, -pd2};
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (2 * m > n || (n == 2 && m == 1)) continue;
@@ -314,28 +201,31 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
     }
   }
 
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   // ---- d = Lambda^{-1} T_B a  (reverse); orders 0, 1 of d were set from rho and 0
   {
     const double ith = 1.0 / th;
     const double isq = 1.0 / sq;
+    // each d_j is read once and feeds the components j, j + e_k and j + 2 e_k of abar (orders 2..N)
 #pragma unroll
     for (int a = 0; a <= N; ++a)
 #pragma unroll
     for (int b = 0; b <= N; ++b)
 #pragma unroll
     for (int c = 0; c <= N; ++c) {
-      const int n = a + b + c;
-      if (n < 2 || n > N) continue;
-      const int i = midx(a, b, c);
-      const double g = ab[i];
-      if (a >= 1) ubar[0] -= isq * g * a * dv(midx(a - 1, b, c));
-      if (b >= 1) ubar[1] -= isq * g * b * dv(midx(a, b - 1, c));
-      if (c >= 1) ubar[2] -= isq * g * c * dv(midx(a, b, c - 1));
-      double t = 0.0;
-      if (a >= 2) t += binom(a, 2) * dv(midx(a - 2, b, c));
-      if (b >= 2) t += binom(b, 2) * dv(midx(a, b - 2, c));
-      if (c >= 2) t += binom(c, 2) * dv(midx(a, b, c - 2));
-      thbar -= g * ((0.5 * n) * ith * dv(i) + ith * t);
+      const int m = a + b + c;
+      if (m > N) continue;
+      const double dj = dv(midx(a, b, c));
+      if (m + 1 >= 2 && m + 1 <= N) {
+        ubar[0] -= isq * ab[midx(a + 1, b, c)] * (a + 1) * dj;
+        ubar[1] -= isq * ab[midx(a, b + 1, c)] * (b + 1) * dj;
+        ubar[2] -= isq * ab[midx(a, b, c + 1)] * (c + 1) * dj;
+      }
+      double t = (m >= 2) ? ab[midx(a, b, c)] * (0.5 * m) : 0.0;
+      if (m + 2 <= N)
+        t += binom(a + 2, 2) * ab[midx(a + 2, b, c)] + binom(b + 2, 2) * ab[midx(a, b + 2, c)] +
+             binom(c + 2, 2) * ab[midx(a, b, c + 2)];
+      thbar -= ith * t * dj;
     }
 #pragma unroll
     for (int n = 2; n <= N; ++n) {

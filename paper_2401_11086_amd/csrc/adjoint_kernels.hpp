@@ -119,18 +119,23 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return out;
 }
 
-// Per-thread vector of M doubles in dynamic LDS, strided by the block size (conflict-free).
+// Work-items per block of the adjoint kernels (one wavefront).
+constexpr int kAdjBlock = 64;
+
+// Per-thread vector of M doubles in dynamic LDS, strided by the block size (conflict-free); the
+// stride is a compile-time constant so that every element address is the thread's base plus an
+// immediate offset.
 struct LdsVec {
   double* base;
-  int stride;
-  __device__ __forceinline__ double operator()(int i) const { return base[i * stride]; }
-  __device__ __forceinline__ void set(int i, double v) const { base[i * stride] = v; }
+  __device__ __forceinline__ double operator()(int i) const { return base[i * kAdjBlock]; }
+  __device__ __forceinline__ void set(int i, double v) const { base[i * kAdjBlock] = v; }
 };
 
 // One adjoint step: lam_t = (d f_{t+1} / d f_t)^T lam_next, per-block partials of dL/dtau.
-// Dynamic LDS: 2 M doubles per work-item (the local moments d and z = Lambda d').
+// Dynamic LDS: 2 M doubles per work-item (the local moments d and z = Lambda d'); blocks of
+// kAdjBlock work-items.
 template <int Q1, int N, bool SHOCK>
-__global__ __launch_bounds__(256) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
+__global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
                                                  const float* __restrict__ lam_next, float* __restrict__ lam_t,
                                                  double* __restrict__ partial) {
   constexpr int M = n_moments(N);
@@ -143,8 +148,8 @@ __global__ __launch_bounds__(256) void k_adjoint(LatticeConst L, StepArgs A, con
 #pragma unroll
   for (int i = 0; i < NT; ++i) tb[i] = 0.0;
   if (active) {
-    const LdsVec dv{lds + threadIdx.x, static_cast<int>(blockDim.x)};
-    const LdsVec zv{lds + static_cast<size_t>(M) * blockDim.x + threadIdx.x, static_cast<int>(blockDim.x)};
+    const LdsVec dv{lds + threadIdx.x};
+    const LdsVec zv{lds + M * kAdjBlock + threadIdx.x};
     Macro mac;
     {
       double d[M];

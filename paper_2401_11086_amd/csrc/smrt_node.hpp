@@ -88,22 +88,25 @@ __device__ __forceinline__ void sym_trace(const double* X, double* T) {
 }
 
 // symmetric product with delta: rank L -> rank L+2,
-//   (delta Y)_alpha = sum_k C(alpha_k, 2) Y_{alpha - 2 e_k} / C(L+2, 2)
+//   (delta Y)_alpha = sum_k C(alpha_k, 2) Y_{alpha - 2 e_k} / C(L+2, 2);
+// sym_delta_at gives component (x, y, L+2-x-y).
+template <int L>
+__device__ __forceinline__ double sym_delta_at(const double* Y, int x, int y) {
+  const int z = L + 2 - x - y;
+  double s = 0.0;
+  if (x >= 2) s += binom(x, 2) * Y[sym_pos(L, x - 2, y)];
+  if (y >= 2) s += binom(y, 2) * Y[sym_pos(L, x, y - 2)];
+  if (z >= 2) s += binom(z, 2) * Y[sym_pos(L, x, y)];
+  return s * (1.0 / binom(L + 2, 2));
+}
+
 template <int L>
 __device__ __forceinline__ void sym_delta(const double* Y, double* P) {
-  constexpr double inv = 1.0 / binom(L + 2, 2);
 #pragma unroll
-  for (int a = 0; a <= L + 2; ++a)
+  for (int x = 0; x <= L + 2; ++x)
 #pragma unroll
-    for (int b = 0; b <= L + 2; ++b) {
-      if (a + b > L + 2) continue;
-      const int c = L + 2 - a - b;
-      double s = 0.0;
-      if (a >= 2) s += binom(a, 2) * Y[sym_pos(L, a - 2, b)];
-      if (b >= 2) s += binom(b, 2) * Y[sym_pos(L, a, b - 2)];
-      if (c >= 2) s += binom(c, 2) * Y[sym_pos(L, a, b)];
-      P[sym_pos(L + 2, a, b)] = s * inv;
-    }
+    for (int y = 0; y <= L + 2; ++y)
+      if (x + y <= L + 2) P[sym_pos(L + 2, x, y)] = sym_delta_at<L>(Y, x, y);
 }
 
 // Traceless projector Q_0^(L) (App. A); for L <= 3 only the k <= 1 term exists.
@@ -157,22 +160,14 @@ __device__ __forceinline__ void irreducible_piece(const double* dn, double* P) {
   }
 }
 
-// D = a D - delta Y  (rank L -> rank L+2, in place on D), the element-wise form of sym_delta
+// D = a D - delta Y  (rank L -> rank L+2, in place on D)
 template <int L>
 __device__ __forceinline__ void sym_delta_update(const double* Y, double a, double* D) {
-  constexpr double inv = 1.0 / binom(L + 2, 2);
 #pragma unroll
   for (int x = 0; x <= L + 2; ++x)
 #pragma unroll
-    for (int y = 0; y <= L + 2; ++y) {
-      if (x + y > L + 2) continue;
-      const int z = L + 2 - x - y;
-      double s = 0.0;
-      if (x >= 2) s += binom(x, 2) * Y[sym_pos(L, x - 2, y)];
-      if (y >= 2) s += binom(y, 2) * Y[sym_pos(L, x, y - 2)];
-      if (z >= 2) s += binom(z, 2) * Y[sym_pos(L, x, y)];
-      D[sym_pos(L + 2, x, y)] = fma(a, D[sym_pos(L + 2, x, y)], -s * inv);
-    }
+    for (int y = 0; y <= L + 2; ++y)
+      if (x + y <= L + 2) D[sym_pos(L + 2, x, y)] = fma(a, D[sym_pos(L + 2, x, y)], -sym_delta_at<L>(Y, x, y));
 }
 
 // eq:SMRT on order n: d'^(n) = sum_m (1 - om_m) d^(n,m) delta^m
