@@ -216,11 +216,13 @@ def time_batched(torch, n_shocks=64, steps=5000, seed=0):
     nodes = lat.n_nodes
     out = {"workload": f"{n_shocks} shocks, Ma~U[1.2,5], Nx~U{{400..2000}} (sum {nodes}), D3Q729, N=5, "
                        f"{steps} steps", "nodes": nodes,
-           "batched": {"launch": {"mode": tune["mode"], "block": tune["block"]}, "ms_per_step": round(ms, 5),
+           "batched": {"launch": {"mode": tune["mode"], "block": tune["block"],
+                                  "lanes_per_node": tune["lanes_per_node"]}, "ms_per_step": round(ms, 5),
                        "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
                        "achieved_GBs": round(8.0 * lat.Q * nodes / (ms / 1e3) / 1e9, 1)},
            "autotune_trials": tune.get("trials")}
-    _progress(f"batched sweep: {ms * 1e3:.1f} us/step ({tune['mode']}, {tune['block']})")
+    _progress(f"batched sweep: {ms * 1e3:.1f} us/step ({tune['mode']}, {tune['block']}, "
+              f"{tune['lanes_per_node']} lanes/node)")
     # the same shocks as separate contexts, one launch per shock per step
     sep = []
     for d, f in zip(doms, fields):

@@ -80,7 +80,9 @@ _SIGS = {
                                         ctypes.c_void_p]),
     "lbsmrt_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "lbsmrt_set_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
-    "lbsmrt_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "lbsmrt_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "lbsmrt_get_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int)]),
     "lbsmrt_destroy": (None, [ctypes.c_void_p]),
     "lbsmrt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lbsmrt_solve_quadrature": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,

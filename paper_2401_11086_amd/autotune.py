@@ -1,5 +1,5 @@
-"""Launch autotuner: picks lbsmrt_set_launch's mode and work-group size by timing
-a few steps of the caller's own lattice, and caches the choice in a JSON file
+"""Launch autotuner: picks lbsmrt_set_launch's mode, work-group size and lanes per node
+by timing a few steps of the caller's own lattice, and caches the choice in a JSON file
 keyed by device, velocity set, order, precision and problem-size bucket."""
 import json
 import math
@@ -7,8 +7,15 @@ import os
 
 import torch
 
-CANDIDATES = [("direct", 64), ("direct", 128), ("direct", 256), ("graph", 64), ("graph", 128), ("graph", 256),
-              ("persistent", 64), ("persistent", 128), ("persistent", 256)]
+CANDIDATES = [(mode, block, lpn) for lpn in (1, 4) for mode in ("direct", "graph", "persistent")
+              for block in (64, 128, 256)]
+
+
+def _candidates(lat):
+    """Lanes per node 4 exists for shock contexts with FP64 contractions only."""
+    shock = any(int(d.get("bc_x", 0)) != 0 for d in lat.domains)
+    ok4 = shock and lat.precision == "fp64_contract"
+    return [c for c in CANDIDATES if c[2] == 1 or ok4]
 
 
 def _cache_path():
@@ -20,7 +27,7 @@ def _key(lat):
     props = torch.cuda.get_device_properties(lat.device)
     arch = getattr(props, "gcnArchName", props.name)
     bucket = int(round(math.log2(max(lat.n_nodes, 1))))
-    return f"{arch}|Q{lat.Q}|N{lat.N}|{lat.precision}|nodes2^{bucket}|dom{len(lat.domains)}"
+    return f"{arch}|Q{lat.Q}|N{lat.N}|{lat.precision}|nodes2^{bucket}|dom{len(lat.domains)}|lpn"
 
 
 def _time(lat, fa, fb, steps):
@@ -37,7 +44,7 @@ def _time(lat, fa, fb, steps):
 
 def autotune(lat, fa, fb, steps=20, graph_steps=32, use_cache=True):
     """Time every candidate on (fa, fb) (their contents are advanced), apply the fastest,
-    and return {'mode', 'block', 'ms_per_step', 'trials'}."""
+    and return {'mode', 'block', 'lanes_per_node', 'ms_per_step', 'trials'}."""
     path = _cache_path()
     key = _key(lat)
     cache = {}
@@ -49,18 +56,18 @@ def autotune(lat, fa, fb, steps=20, graph_steps=32, use_cache=True):
             cache = {}
     if use_cache and key in cache:
         best = cache[key]
-        lat.set_launch(best["mode"], best["block"], graph_steps)
+        lat.set_launch(best["mode"], best["block"], graph_steps, best["lanes_per_node"])
         return dict(best, cached=True)
     trials = []
-    for mode, block in CANDIDATES:
+    for mode, block, lpn in _candidates(lat):
         try:
-            lat.set_launch(mode, block, graph_steps)
+            lat.set_launch(mode, block, graph_steps, lpn)
         except Exception:
             continue
-        trials.append((mode, block, _time(lat, fa, fb, steps)))
-    mode, block, ms = min(trials, key=lambda t: t[2])
-    lat.set_launch(mode, block, graph_steps)
-    best = {"mode": mode, "block": block, "ms_per_step": round(ms, 5)}
+        trials.append((mode, block, lpn, _time(lat, fa, fb, steps)))
+    mode, block, lpn, ms = min(trials, key=lambda t: t[3])
+    lat.set_launch(mode, block, graph_steps, lpn)
+    best = {"mode": mode, "block": block, "lanes_per_node": lpn, "ms_per_step": round(ms, 5)}
     if use_cache:
         cache[key] = best
         try:
@@ -69,4 +76,5 @@ def autotune(lat, fa, fb, steps=20, graph_steps=32, use_cache=True):
                 json.dump(cache, fh, indent=1, sort_keys=True)
         except OSError:
             pass
-    return dict(best, trials=[{"mode": m, "block": b, "ms": round(t, 5)} for m, b, t in trials], cached=False)
+    return dict(best, trials=[{"mode": m, "block": b, "lanes_per_node": k, "ms": round(t, 5)}
+                              for m, b, k, t in trials], cached=False)

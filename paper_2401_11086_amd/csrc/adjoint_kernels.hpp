@@ -8,20 +8,25 @@ constexpr int kTauCols = (kMaxN + 1) * 3;   // dL/dtau[n][m] flattened as n*3+m
 
 // Scatter of mu = P^T abar to the streaming sources: out[q][x - s_q] = sum_alpha He_alpha(c_q) abar_alpha.
 // Populations whose source was a ghost cell (shock ends) are skipped.
-template <int Q1, int N, bool SHOCK>
+// LPN > 1: each lane of a node's group scatters the slabs ix = sub, sub + LPN, ... with the
+// uniform pass count of gather_project64; a lane with no slab left repeats the last one, storing
+// the values its owner stores to the same addresses in the same instruction.
+template <int Q1, int N, bool SHOCK, int LPN = 1>
 LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull<Q1>& P,
                                                              const double (&ab)[n_moments(N)],
                                                              float* __restrict__ out, long long stride) {
   constexpr int p = Q1 / 2;
   constexpr int P2 = n_sym(N);
 #pragma unroll 1
-  for (int ix = 0; ix < Q1; ++ix) {
-    const int xs = source_x<Q1>(L, P, ix);
+  for (int k = 0; k < (Q1 + LPN - 1) / LPN; ++k) {
+    const int ixr = (LPN > 1 ? P.sub : 0) + k * LPN;
+    const int ix = (LPN == 1 || ixr < Q1) ? ixr : Q1 - 1;
+    const int xs = source_x_e<Q1>(L, P, abscissa_of<Q1, LPN>(L, ix));
     if (SHOCK && xs < 0) continue;
-    const unsigned xoff = static_cast<unsigned>(P.row + xs) * 4u;
+    const unsigned xoff = (LPN == 1 ? 0u : static_cast<unsigned>(ix * Q1 * Q1) * static_cast<unsigned>(stride) * 4u) +
+                          static_cast<unsigned>(P.row + xs) * 4u;
     double hx[N + 1];
-#pragma unroll
-    for (int n = 0; n <= N; ++n) hx[n] = L.He64[ix][n];
+    table_row<Q1, N, LPN>(L.He64, ix, hx);
     double u2[P2];
 #pragma unroll
     for (int ay = 0; ay <= N; ++ay)
@@ -34,7 +39,7 @@ LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull
           if (ax + ay + az <= N) s = fma(ab[midx(ax, ay, az)], hx[ax], s);
         u2[pair_pos(ay, az)] = s;
       }
-    float* __restrict__ slab = out + static_cast<size_t>(ix * Q1 * Q1) * stride;
+    float* __restrict__ slab = LPN == 1 ? out + static_cast<size_t>(ix * Q1 * Q1) * stride : out;
     auto zline = [&](int iy, const double (&v)[N + 1]) {
       float* __restrict__ line = slab + static_cast<size_t>(iy * Q1) * stride;
       const unsigned yoff = xoff + P.yo[iy];
@@ -134,7 +139,7 @@ struct LdsVec {
 // One adjoint step: lam_t = (d f_{t+1} / d f_t)^T lam_next, per-block partials of dL/dtau.
 // Dynamic LDS: 2 M doubles per work-item (the local moments d and z = Lambda d'); blocks of
 // kAdjBlock work-items.
-template <int Q1, int N, bool SHOCK>
+template <int Q1, int N, bool SHOCK, int LPN = 1>
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
                                                  const float* __restrict__ lam_next, float* __restrict__ lam_t,
                                                  double* __restrict__ partial) {
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs 
   extern __shared__ double lds[];
   __shared__ double red[256];
   Pull<Q1> P;
-  const bool active = make_pull<Q1>(L, A, P);
+  const bool active = make_pull<Q1, LPN>(L, A, P);
   double tb[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) tb[i] = 0.0;
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs 
     {
       double d[M];
       double S[5];
-      gather_project64<Q1, N, SHOCK>(L, A, f_t, P, d);
+      gather_project64<Q1, N, SHOCK, LPN>(L, A, f_t, P, d);
       sums_from_a<N>(d, L, S);
       mac = macro_from_sums(L, S, A.err);
       mac.tsc = P.tsc;
@@ -163,10 +168,15 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs 
       for (int i = 0; i < M; ++i) dv.set(i, d[i]);
     }
     double ab[M];
-    own_project64<Q1, N, true>(L, lam_next, A.stride, P.node, ab);
+    own_project64<Q1, N, true, LPN>(L, lam_next, A.stride, P.node, ab, P.sub);
     node_adjoint<N>(L, mac, dv, zv, ab, tb);
-    scatter_transpose_projection<Q1, N, SHOCK>(L, P, ab, lam_t, A.stride);
+    scatter_transpose_projection<Q1, N, SHOCK, LPN>(L, P, ab, lam_t, A.stride);
+    // every lane of a group zeroes the same out-flowing populations (identical stores)
     if (SHOCK && P.bc_x == 1) zero_outflow<Q1>(L, P, lam_t, A.stride);
+    if (LPN > 1 && P.sub != 0) {
+#pragma unroll
+      for (int i = 0; i < NT; ++i) tb[i] = 0.0;   // the group's dL/dtau counted once
+    }
   }
 #pragma unroll
   for (int i = 0; i < NT; ++i) {

@@ -65,15 +65,19 @@ struct Pull {
   unsigned yo[Q1];           // byte offset of source row ys*nx per iy
   unsigned zo[Q1];           // byte offset of source plane zs*nx*ny per iz
   int gcol;                  // left ghost column
+  int sub;                   // lane of this work-item within its node's group (0 .. LPN-1)
   double tsc;                // tau scale of the domain
 };
 
-template <int Q1>
+// Node of this work-item: LPN consecutive work-items share one node (block b covers nodes
+// first .. first + blockDim.x / LPN - 1 of its domain).
+template <int Q1, int LPN = 1>
 __device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs& A, Pull<Q1>& P,
                                           int work_block = -1) {
   const BlockDev bd = A.blocks[work_block < 0 ? static_cast<int>(blockIdx.x) : work_block];
   const DomainDev D = A.doms[bd.dom];
-  const int local = bd.first + static_cast<int>(threadIdx.x);
+  const int local = bd.first + static_cast<int>(threadIdx.x) / LPN;
+  P.sub = static_cast<int>(threadIdx.x) % LPN;
   const int nxy = D.nx * D.ny;
   if (local >= nxy * D.nz) return false;
   const int x = local % D.nx;
@@ -100,6 +104,50 @@ __device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs&
 template <int Q1>
 __device__ __forceinline__ int source_x(const LatticeConst& L, const Pull<Q1>& P, int ix) {
   int xs = P.x - (L.e[ix] + L.k[0]);
+  if (P.bc_x == 0) {
+    xs %= P.nx;
+    if (xs < 0) xs += P.nx;
+    return xs;
+  }
+  return xs < 0 ? -1 : (xs >= P.nx ? -2 : xs);
+}
+
+// Row ix of a per-abscissa table.  With ix uniform across the wavefront (LPN = 1) this is a
+// plain (scalar) lookup; with ix differing between lanes it is a select over the Q1 rows, which
+// keeps the table in scalar registers.
+template <int Q1, int N, int LPN, class T, int R, int C>
+__device__ __forceinline__ void table_row(const T (&tab)[R][C], int ix, T (&out)[N + 1]) {
+  if constexpr (LPN == 1) {
+#pragma unroll
+    for (int n = 0; n <= N; ++n) out[n] = tab[ix][n];
+  } else {
+#pragma unroll
+    for (int n = 0; n <= N; ++n) out[n] = tab[0][n];
+#pragma unroll
+    for (int j = 1; j < Q1; ++j) {
+      const bool hit = ix == j;
+#pragma unroll
+      for (int n = 0; n <= N; ++n) out[n] = hit ? tab[j][n] : out[n];
+    }
+  }
+}
+
+template <int Q1, int LPN>
+__device__ __forceinline__ int abscissa_of(const LatticeConst& L, int ix) {
+  if constexpr (LPN == 1) {
+    return L.e[ix];
+  } else {
+    int e = L.e[0];
+#pragma unroll
+    for (int j = 1; j < Q1; ++j) e = ix == j ? L.e[j] : e;
+    return e;
+  }
+}
+
+// source_x for a given abscissa e of the population column
+template <int Q1>
+__device__ __forceinline__ int source_x_e(const LatticeConst& L, const Pull<Q1>& P, int e) {
+  int xs = P.x - (e + L.k[0]);
   if (P.bc_x == 0) {
     xs %= P.nx;
     if (xs < 0) xs += P.nx;
@@ -264,6 +312,31 @@ __device__ __forceinline__ void fold_slab_project(const LatticeConst& L, const f
   }
 }
 
+// Sum over the LPN (2 or 4) consecutive lanes of a group, every lane receiving the total, by
+// DPP quad permutations (lane ^ 1, then lane ^ 2).  Floating-point addition is commutative, so
+// all lanes of a group end with bit-identical sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad_perm_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                        static_cast<unsigned>(lo));
+}
+
+template <int LPN, int M>
+__device__ __forceinline__ void group_allreduce(double (&a)[M]) {
+  static_assert(LPN == 2 || LPN == 4, "groups of 2 or 4 lanes");
+  constexpr int kSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
+  constexpr int kSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int i = 0; i < M; ++i) a[i] += dpp_quad_perm_f64<kSwap1>(a[i]);
+  if constexpr (LPN == 4) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) a[i] += dpp_quad_perm_f64<kSwap2>(a[i]);
+  }
+}
+
 // As fold_slab_project, with the populations of each z line fetched just before it is folded
 // (load(iy, line) fills line[iz]); keeps at most two lines of a slab in registers.
 template <int Q1, int N, bool RW, class LineLoad>
@@ -302,24 +375,32 @@ __device__ __forceinline__ void fold_slab_project_lines(const LatticeConst& L, c
 
 // FP64 projection of a node's own populations (no streaming) with table T:
 //   out[ax,ay,az] = sum_{ix,iy,iz} T_ax(c_ix) T_ay(c_iy) T_az(c_iz) v[q]
-template <int Q1, int N, bool RW>
+template <int Q1, int N, bool RW, int LPN = 1>
 LBSMRT_PHASE void own_project64(const LatticeConst& L, const float* __restrict__ v, long long stride,
-                                              int node, double (&out)[n_moments(N)]) {
+                                              int node, double (&out)[n_moments(N)], int sub = 0) {
   constexpr int P2 = n_sym(N);
-  const unsigned off = static_cast<unsigned>(node) * 4u;
 #pragma unroll
   for (int i = 0; i < n_moments(N); ++i) out[i] = 0.0;
+  // LPN > 1: the slab split of gather_project64 (uniform pass count, zero weight on a repeat)
 #pragma unroll 1
-  for (int ix = 0; ix < Q1; ++ix) {
-    const float* __restrict__ vx = v + static_cast<size_t>(ix * Q1 * Q1) * stride;
+  for (int k = 0; k < (Q1 + LPN - 1) / LPN; ++k) {
+    const int ixr = (LPN > 1 ? sub : 0) + k * LPN;
+    const int ix = (LPN == 1 || ixr < Q1) ? ixr : Q1 - 1;
+    const float* __restrict__ vx = LPN == 1 ? v + static_cast<size_t>(ix * Q1 * Q1) * stride : v;
+    const unsigned off = (LPN == 1 ? 0u : static_cast<unsigned>(ix * Q1 * Q1) * static_cast<unsigned>(stride) * 4u) +
+                         static_cast<unsigned>(node) * 4u;
     float gs[Q1 * Q1];
 #pragma unroll
     for (int qs = 0; qs < Q1 * Q1; ++qs) gs[qs] = load_at(vx + static_cast<size_t>(qs) * stride, off);
     double t2[P2];
     fold_slab_project<Q1, N, RW>(L, gs, t2);
     double hx[N + 1];
+    if constexpr (RW) table_row<Q1, N, LPN>(L.Rw64, ix, hx);
+    else table_row<Q1, N, LPN>(L.He64, ix, hx);
+    if (LPN > 1 && ixr >= Q1) {
 #pragma unroll
-    for (int n = 0; n <= N; ++n) hx[n] = tab<RW>(L, ix, n);
+      for (int n = 0; n <= N; ++n) hx[n] = 0.0;
+    }
 #pragma unroll
     for (int ax = 0; ax <= N; ++ax)
 #pragma unroll
@@ -328,11 +409,12 @@ LBSMRT_PHASE void own_project64(const LatticeConst& L, const float* __restrict__
         for (int az = 0; az <= N; ++az)
           if (ax + ay + az <= N) out[midx(ax, ay, az)] = fma(t2[pair_pos(ay, az)], hx[ax], out[midx(ax, ay, az)]);
   }
+  if constexpr (LPN > 1) group_allreduce<LPN, n_moments(N)>(out);
 }
 
 // Gather + FP64 projection (eq:an): a[ax,ay,az] = sum_ix He_ax(c_ix) t2_ix[ay,az].
 // rho = a_0, j = a_1 and sum g |c|^2 = sum_k a_{2 e_k} + 3 rho come out exactly in FP64.
-template <int Q1, int N, bool SHOCK>
+template <int Q1, int N, bool SHOCK, int LPN = 1>
 LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
                                                  const float* __restrict__ f, const Pull<Q1>& P,
                                                  double (&a)[Shape<Q1, N>::M]) {
@@ -340,15 +422,23 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
 #pragma unroll
   for (int i = 0; i < Shape<Q1, N>::M; ++i) a[i] = 0.0;
 #pragma unroll 1
-  for (int ix = 0; ix < Q1; ++ix) {
-    const int xs = source_x<Q1>(L, P, ix);
-    const float* __restrict__ fx = f + static_cast<size_t>(ix * Q1 * Q1) * A.stride;
+  // With LPN > 1 every lane makes the same number of passes (uniform control flow); a lane with
+  // no slab left repeats the last slab with zero weight.
+  for (int k = 0; k < (Q1 + LPN - 1) / LPN; ++k) {
+    const int ixr = (LPN > 1 ? P.sub : 0) + k * LPN;
+    const int ix = (LPN == 1 || ixr < Q1) ? ixr : Q1 - 1;
+    const int xs = source_x_e<Q1>(L, P, abscissa_of<Q1, LPN>(L, ix));
+    // slab ix: a uniform base pointer when every lane works on the same slab; otherwise the
+    // slab's offset goes into each lane's 32-bit byte offset (Q * stride * 4 < 2^32 then)
+    const float* __restrict__ fx = LPN == 1 ? f + static_cast<size_t>(ix * Q1 * Q1) * A.stride : f;
+    const unsigned slab_off = LPN == 1 ? 0u : static_cast<unsigned>(ix * Q1 * Q1) * static_cast<unsigned>(A.stride) * 4u;
     // shock ends: every lane loads from an in-domain address; lanes whose source is a ghost
     // cell then take the ghost value, on a path only waves that touch an end execute
     const bool ghost = SHOCK && xs < 0;
-    const unsigned xoff = static_cast<unsigned>(P.row + (ghost ? 0 : xs)) * 4u;
+    const unsigned xoff = slab_off + static_cast<unsigned>(P.row + (ghost ? 0 : xs)) * 4u;
     const bool any_ghost = SHOCK && __any(ghost);
-    const float* __restrict__ gcol = A.ghosts + P.gcol + (xs == -2 ? 1 : 0);
+    // ghost value of population (ix, iy, iz): ghosts[(ix Q1^2 + iy Q1 + iz) n_ghost + column]
+    const unsigned goff = static_cast<unsigned>(ix * Q1 * Q1 * A.n_ghost + P.gcol + (xs == -2 ? 1 : 0)) * 4u;
     auto load = [&](int iy, float (&line)[Q1]) {
       const unsigned xyoff = xoff + P.yo[iy];
 #pragma unroll
@@ -357,7 +447,7 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
       if (any_ghost) {
 #pragma unroll
         for (int iz = 0; iz < Q1; ++iz) {
-          const float gv = gcol[static_cast<size_t>(ix * Q1 * Q1 + iy * Q1 + iz) * A.n_ghost];
+          const float gv = load_at(A.ghosts + static_cast<size_t>(iy * Q1 + iz) * A.n_ghost, goff);
           line[iz] = ghost ? gv : line[iz];
         }
       }
@@ -365,8 +455,11 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
     double t2[P2];
     fold_slab_project_lines<Q1, N, false>(L, load, t2);
     double hx[N + 1];
+    table_row<Q1, N, LPN>(L.He64, ix, hx);
+    if (LPN > 1 && ixr >= Q1) {
 #pragma unroll
-    for (int n = 0; n <= N; ++n) hx[n] = L.He64[ix][n];
+      for (int n = 0; n <= N; ++n) hx[n] = 0.0;
+    }
 #pragma unroll
     for (int ax = 0; ax <= N; ++ax)
 #pragma unroll
@@ -375,6 +468,7 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
         for (int az = 0; az <= N; ++az)
           if (ax + ay + az <= N) a[midx(ax, ay, az)] = fma(t2[pair_pos(ay, az)], hx[ax], a[midx(ax, ay, az)]);
   }
+  if constexpr (LPN > 1) group_allreduce<LPN, Shape<Q1, N>::M>(a);
 }
 
 // One z line of the rebuild: f[iz] = sum_az Rw_az(iz) v[az], stored as FP32.
@@ -402,17 +496,24 @@ __device__ __forceinline__ void fold_line_store(const LatticeConst& L, const dou
 }
 
 // Rebuild (eq:fi with 1/alpha!) in FP64, folded in y and z, and store to the own node.
-template <int Q1, int N>
+template <int Q1, int N, int LPN = 1>
 LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[Shape<Q1, N>::M],
-                                                    float* __restrict__ out, long long stride, int node) {
+                                                    float* __restrict__ out, long long stride, int node,
+                                                    int sub = 0) {
   constexpr int p = Q1 / 2;
   constexpr int P2 = Shape<Q1, N>::P2;
-  const unsigned off = static_cast<unsigned>(node) * 4u;
+  // With LPN > 1 every lane makes the same number of passes; a lane with no slab left rebuilds
+  // and stores the last slab again: the same values the lane that owns it stores to the same
+  // addresses in the same instruction.
 #pragma unroll 1
-  for (int ix = 0; ix < Q1; ++ix) {
+  for (int k = 0; k < (Q1 + LPN - 1) / LPN; ++k) {
+    const int ixr = (LPN > 1 ? sub : 0) + k * LPN;
+    const int ix = (LPN == 1 || ixr < Q1) ? ixr : Q1 - 1;
     double rx[N + 1];
-#pragma unroll
-    for (int n = 0; n <= N; ++n) rx[n] = L.Rw64[ix][n];
+    table_row<Q1, N, LPN>(L.Rw64, ix, rx);
+    // as in gather_project64: uniform slab pointer, or the slab offset in the lane's byte offset
+    const unsigned off = (LPN == 1 ? 0u : static_cast<unsigned>(ix * Q1 * Q1) * static_cast<unsigned>(stride) * 4u) +
+                         static_cast<unsigned>(node) * 4u;
     double u2[P2];
 #pragma unroll
     for (int ay = 0; ay <= N; ++ay)
@@ -425,7 +526,7 @@ LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[
           if (ax + ay + az <= N) s = fma(ap[midx(ax, ay, az)], rx[ax], s);
         u2[pair_pos(ay, az)] = s;
       }
-    float* __restrict__ slab = out + static_cast<size_t>(ix * Q1 * Q1) * stride;
+    float* __restrict__ slab = LPN == 1 ? out + static_cast<size_t>(ix * Q1 * Q1) * stride : out;
     {
       double v[N + 1];
 #pragma unroll
@@ -589,17 +690,21 @@ __device__ __forceinline__ void reconstruct_store(const LatticeConst& L, const f
 enum : int { kPrecFp32 = 0, kPrecFp64 = 2 };
 
 // One node of the fused step (work-block `wb` of the block table, or blockIdx.x when wb < 0).
-template <int Q1, int N, bool SHOCK, int PREC>
+// LPN > 1 (FP64 contractions only): LPN lanes share a node, each gathering and storing the
+// x-slabs ix = sub, sub + LPN, ...; the moments are summed across the group and every lane
+// runs the (identical) collision.
+template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1>
 __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const StepArgs& A,
                                                     const float* __restrict__ fsrc, float* __restrict__ fdst,
                                                     int wb) {
+  static_assert(LPN == 1 || PREC == kPrecFp64, "lanes per node > 1 needs the FP64 contractions");
   constexpr int M = Shape<Q1, N>::M;
   Pull<Q1> P;
-  if (!make_pull<Q1>(L, A, P, wb)) return;
+  if (!make_pull<Q1, LPN>(L, A, P, wb)) return;
   double d[M];
   double S[5];
   if constexpr (PREC == kPrecFp64) {
-    gather_project64<Q1, N, SHOCK>(L, A, fsrc, P, d);
+    gather_project64<Q1, N, SHOCK, LPN>(L, A, fsrc, P, d);
     sums_from_a<N>(d, L, S);
   } else {
     float a[M];
@@ -617,7 +722,7 @@ __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const
   relax<N>(d, L, mac.rho, mac.tsc);
   to_lattice<N>(d, mac);
   if constexpr (PREC == kPrecFp64) {
-    reconstruct_store64<Q1, N>(L, d, fdst, A.stride, P.node);
+    reconstruct_store64<Q1, N, LPN>(L, d, fdst, A.stride, P.node, P.sub);
   } else {
     float ap[M];
 #pragma unroll
@@ -626,16 +731,16 @@ __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const
   }
 }
 
-template <int Q1, int N, bool SHOCK, int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_collide_stream(LatticeConst L, StepArgs A, const float* __restrict__ fsrc,
-                                                        float* __restrict__ fdst) {
-  collide_stream_node<Q1, N, SHOCK, PREC>(L, A, fsrc, fdst, -1);
+template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_collide_stream(
+    LatticeConst L, StepArgs A, const float* __restrict__ fsrc, float* __restrict__ fdst) {
+  collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, fsrc, fdst, -1);
 }
 
 // Persistent form: every work-group strides over the block table, n_steps times, with a grid-wide
 // barrier between steps (cooperative launch, so all work-groups are resident).  Step t reads
 // fa when t is even and fb when odd, as lbsmrt_step does.
-template <int Q1, int N, bool SHOCK, int PREC>
+template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1>
 __global__ __launch_bounds__(256) void k_collide_persistent(LatticeConst L, StepArgs A, float* fa, float* fb,
                                                             int n_blocks, int n_steps) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
@@ -643,7 +748,7 @@ __global__ __launch_bounds__(256) void k_collide_persistent(LatticeConst L, Step
     const float* src = (t & 1) ? fb : fa;
     float* dst = (t & 1) ? fa : fb;
     for (int wb = blockIdx.x; wb < n_blocks; wb += gridDim.x)
-      collide_stream_node<Q1, N, SHOCK, PREC>(L, A, src, dst, wb);
+      collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, src, dst, wb);
     grid.sync();
   }
 }

@@ -27,6 +27,7 @@ struct lbsmrt_ctx {
   long long n_nodes = 0, stride = 0;
   bool shock = false;
   int block = 256;
+  int lpn = 1;                       // lanes per node of the step kernel (1, or 4: shocks, FP64)
   int n_blocks = 0;
   int n_ghost = 0;
   DomainDev* d_doms = nullptr;
@@ -36,6 +37,9 @@ struct lbsmrt_ctx {
   int* d_err = nullptr;
   double* d_partial = nullptr;   // [n_blocks_adj][kTauCols] per-block partial sums
   BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
+  BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
+  int n_blocks_adj4 = 0;
+  bool lpn4_ok = false;              // shock domains, FP64 contractions, state below 4 GiB
   double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
   // launch mode of lbsmrt_step
   int mode = LBSMRT_LAUNCH_DIRECT;
@@ -72,7 +76,10 @@ template <int Q1, int N>
 struct Launch {
   template <int PREC>
   static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
-    if (c->shock)
+    if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 4>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
+                         A, src, dst);
+    else if (c->shock)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, PREC>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src,
                          dst);
     else
@@ -88,27 +95,33 @@ struct Launch {
     return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC>);
   }
   static const void* persistent(const lbsmrt_ctx* c) {
+    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
+      return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
     if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
     return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
   }
   static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s) {
     if (c->shock)
-      hipLaunchKernelGGL((k_moments<Q1, N, true>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, out, mask,
+      hipLaunchKernelGGL((k_moments<Q1, N, true>), dim3(c->n_blocks), dim3(c->block / c->lpn), 0, s, c->L, A, f, out, mask,
                          c->n_nodes);
     else
-      hipLaunchKernelGGL((k_moments<Q1, N, false>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, f, out, mask,
+      hipLaunchKernelGGL((k_moments<Q1, N, false>), dim3(c->n_blocks), dim3(c->block / c->lpn), 0, s, c->L, A, f, out, mask,
                          c->n_nodes);
   }
   static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
                       hipStream_t s) {
-    const size_t lds = 2 * sizeof(double) * n_moments(N) * 64;
-    if (c->shock)
-      hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(c->n_blocks_adj), dim3(64), lds, s, c->L, A, f_t, lam_next,
+    const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
+    const int nb = c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj;
+    if (c->shock && c->lpn == 4)
+      hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
+                         lam_t, c->d_partial);
+    else if (c->shock)
+      hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
                          lam_t, c->d_partial);
     else
-      hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), lds, s, c->L, A, f_t, lam_next,
+      hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
                          lam_t, c->d_partial);
-    hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, c->n_blocks_adj,
+    hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
                        n_tau_slots(N), c->d_stage);
     hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(64), 0, s, c->d_stage, kReduceBlocks, A.dtau);
   }
@@ -168,10 +181,16 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_err);
   (void)hipFree(c->d_partial);
   (void)hipFree(c->d_blocks_adj);
+  (void)hipFree(c->d_blocks_adj4);
   (void)hipFree(c->d_stage);
   delete c;
 }
 
+// Contexts up to this many nodes start with four lanes per node (when eligible): with one lane
+// per node they would occupy at most a quarter of the 1024 SIMDs of the chip.
+constexpr long long kSmallContextNodes = 16384;
+
+// Work-group table: consecutive runs of `bs` nodes of each domain.
 std::vector<BlockDev> block_table(const std::vector<lbsmrt_domain>& doms, int bs) {
   std::vector<BlockDev> bl;
   for (size_t i = 0; i < doms.size(); ++i) {
@@ -306,10 +325,20 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (off >= (1LL << 30)) { free_ctx(c); return LBSMRT_E_ARG; }   // 32-bit node offsets in the kernels
   c->stride = (off + 63) / 64 * 64;
   c->block = (max_local >= 4096) ? 256 : 64;
-  std::vector<BlockDev> bl = block_table(c->doms, c->block);
+  // Shock tubes with few nodes fill a small part of the GPU, and each wavefront's serial work
+  // sets the step time: start with four lanes per node there (lbsmrt_set_launch can change it).
+  // (the split kernels address a slab by a 32-bit byte offset from the start of f)
+  c->lpn4_ok = c->shock && c->precision == LBSMRT_FP64_CONTRACT &&
+               static_cast<long long>(c->Q) * c->stride * 4 < (1LL << 32);
+  if (c->lpn4_ok && off <= kSmallContextNodes) c->lpn = 4;
+  std::vector<BlockDev> bl = block_table(c->doms, c->block / c->lpn);
   c->n_blocks = static_cast<int>(bl.size());
-  std::vector<BlockDev> bla = block_table(c->doms, 64);
+  std::vector<BlockDev> bla = block_table(c->doms, kAdjBlock);
   c->n_blocks_adj = static_cast<int>(bla.size());
+  std::vector<BlockDev> bla4;
+  if (c->lpn4_ok) bla4 = block_table(c->doms, kAdjBlock / 4);
+  c->n_blocks_adj4 = static_cast<int>(bla4.size());
+  const size_t partial_rows = static_cast<size_t>(std::max(c->n_blocks_adj, c->n_blocks_adj4));
   c->n_ghost = 2 * n_domains;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -320,9 +349,10 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (hipMalloc(&c->d_ghost, sizeof(float) * c->Q * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_ghost_fields, sizeof(double) * 5 * c->n_ghost) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess) return fail(LBSMRT_E_NOMEM);
-  if (hipMalloc(&c->d_partial, sizeof(double) * kTauCols * static_cast<size_t>(c->n_blocks_adj)) != hipSuccess)
-    return fail(LBSMRT_E_NOMEM);
+  if (hipMalloc(&c->d_partial, sizeof(double) * kTauCols * partial_rows) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_blocks_adj, sizeof(BlockDev) * bla.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (!bla4.empty() && hipMalloc(&c->d_blocks_adj4, sizeof(BlockDev) * bla4.size()) != hipSuccess)
+    return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_stage, sizeof(double) * kTauCols * kReduceBlocks) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
   std::vector<double> gf(5 * c->n_ghost, 0.0);
@@ -342,6 +372,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       hipMemcpyAsync(c->d_blocks, bl.data(), sizeof(BlockDev) * bl.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(c->d_blocks_adj, bla.data(), sizeof(BlockDev) * bla.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
+      (!bla4.empty() && hipMemcpyAsync(c->d_blocks_adj4, bla4.data(), sizeof(BlockDev) * bla4.size(),
+                                       hipMemcpyHostToDevice, s) != hipSuccess) ||
       hipMemcpyAsync(c->d_ghost_fields, gf.data(), sizeof(double) * gf.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       hipMemsetAsync(c->d_err, 0, sizeof(int), s) != hipSuccess)
@@ -425,17 +457,21 @@ lbsmrt_status lbsmrt_step(lbsmrt_ctx* c, float* f_a, float* f_b, int n_steps, vo
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 
-lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int graph_steps) {
+lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int graph_steps, int lanes_per_node) {
   if (!c) return LBSMRT_E_ARG;
   if (mode != LBSMRT_LAUNCH_DIRECT && mode != LBSMRT_LAUNCH_GRAPH && mode != LBSMRT_LAUNCH_PERSISTENT)
     return LBSMRT_E_ARG;
   if (block_size != 0 && block_size != 64 && block_size != 128 && block_size != 256) return LBSMRT_E_ARG;
   if (mode == LBSMRT_LAUNCH_GRAPH && (graph_steps < 2 || graph_steps > 4096 || (graph_steps & 1)))
     return LBSMRT_E_ARG;
+  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 4) return LBSMRT_E_ARG;
+  if (lanes_per_node == 4 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
   drop_graph(c);
-  if (block_size != 0 && block_size != c->block) {
-    std::vector<BlockDev> bl = block_table(c->doms, block_size);
+  const int bs = block_size != 0 ? block_size : c->block;
+  const int lpn = lanes_per_node != 0 ? lanes_per_node : c->lpn;
+  if (bs != c->block || lpn != c->lpn) {
+    std::vector<BlockDev> bl = block_table(c->doms, bs / lpn);
     BlockDev* nb = nullptr;
     if (hipMalloc(&nb, sizeof(BlockDev) * bl.size()) != hipSuccess) return LBSMRT_E_NOMEM;
     if (hipMemcpy(nb, bl.data(), sizeof(BlockDev) * bl.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -445,7 +481,8 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
     (void)hipFree(c->d_blocks);
     c->d_blocks = nb;
     c->n_blocks = static_cast<int>(bl.size());
-    c->block = block_size;
+    c->block = bs;
+    c->lpn = lpn;
   }
   if (mode == LBSMRT_LAUNCH_PERSISTENT) {
     const void* fn = nullptr;
@@ -459,6 +496,14 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   }
   c->graph_pairs = mode == LBSMRT_LAUNCH_GRAPH ? graph_steps / 2 : 0;
   c->mode = mode;
+  return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_get_launch(const lbsmrt_ctx* c, int* mode, int* block_size, int* lanes_per_node) {
+  if (!c) return LBSMRT_E_ARG;
+  if (mode) *mode = c->mode;
+  if (block_size) *block_size = c->block;
+  if (lanes_per_node) *lanes_per_node = c->lpn;
   return LBSMRT_OK;
 }
 
@@ -501,7 +546,7 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* 
   if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   StepArgs A = step_args(c);
-  A.blocks = c->d_blocks_adj;
+  A.blocks = c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj;
   A.dtau = dL_dtau;
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, s); });
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;

@@ -133,11 +133,22 @@ class Lattice:
                 arr[n * 3 + m] = float(self.tau.get((n, m), 1.0))
         C.check(C.lib().lbsmrt_set_tau(self._h, arr), "lbsmrt_set_tau")
 
-    def set_launch(self, mode="direct", block_size=0, graph_steps=64):
-        """mode: 'direct', 'graph' or 'persistent' (see include/lbsmrt.h); block_size 64/128/256 or 0."""
+    def set_launch(self, mode="direct", block_size=0, graph_steps=64, lanes_per_node=0):
+        """mode: 'direct', 'graph' or 'persistent'; block_size 64/128/256 (0 keeps it);
+        lanes_per_node 1 or 4 (0 keeps it; 4 for shock contexts with FP64 contractions).
+        See lbsmrt_set_launch in include/lbsmrt.h."""
         m = {"direct": C.LAUNCH_DIRECT, "graph": C.LAUNCH_GRAPH, "persistent": C.LAUNCH_PERSISTENT}[mode]
-        C.check(C.lib().lbsmrt_set_launch(self._h, m, int(block_size), int(graph_steps)), "lbsmrt_set_launch")
-        self.launch = (mode, block_size, graph_steps)
+        C.check(C.lib().lbsmrt_set_launch(self._h, m, int(block_size), int(graph_steps), int(lanes_per_node)),
+                "lbsmrt_set_launch")
+        self.launch = (mode, block_size, graph_steps, lanes_per_node)
+
+    def launch_settings(self):
+        """{'mode', 'block', 'lanes_per_node'} as the library holds them."""
+        m, b, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        C.check(C.lib().lbsmrt_get_launch(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(k)),
+                "lbsmrt_get_launch")
+        names = {C.LAUNCH_DIRECT: "direct", C.LAUNCH_GRAPH: "graph", C.LAUNCH_PERSISTENT: "persistent"}
+        return {"mode": names[m.value], "block": b.value, "lanes_per_node": k.value}
 
     def sync(self):
         """Wait for the current stream; raise if a node left the validity region."""

@@ -114,3 +114,80 @@ def test_batched_shock_matches_oracle_one_step(torch):
         fo = O.step(f0[:, off:off + nx].astype(np.float64).reshape(-1, 1, 1, nx), model, dom)
         g = f1[:, off:off + nx].reshape(fo.shape)
         assert np.abs(g - fo).max() / np.abs(fo).max() < 1e-5, i
+
+
+@pytest.mark.parametrize("mode,block", [("direct", 64), ("direct", 256), ("graph", 128), ("persistent", 64)])
+def test_four_lanes_per_node(torch, mode, block):
+    """lanes_per_node = 4 (each node's x-slabs split over a quad of lanes): 13 steps agree with
+    lanes_per_node = 1 to float32 rounding (the FP64 projection sums run in another order), equal
+    the direct launch with the same split bitwise, and leave the moment read-out unchanged."""
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    f0 = lat.equilibrium(fl)
+    n = lat.n_nodes
+    f0[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=21), dtype=torch.float32, device="cuda")
+    lat.set_launch("direct", 64, 64, 1)
+    ra, rb = lat.new_state(), lat.new_state()
+    ra.copy_(f0)
+    ref = lat.step(ra, rb, 13)
+    mom_ref = lat.moments(ref).clone()
+    lat.set_launch("direct", block, 64, 4)
+    da, db = lat.new_state(), lat.new_state()
+    da.copy_(f0)
+    direct4 = lat.step(da, db, 13)
+    lat.set_launch(mode, block, 4, 4)
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    out = lat.step(fa, fb, 13)
+    mom = lat.moments(ref)
+    lat.sync()
+    assert torch.equal(out[:, :n], direct4[:, :n])
+    err = float((out[:, :n].double() - ref[:, :n].double()).abs().max() / ref[:, :n].double().abs().max())
+    print(f"lanes_per_node 4 vs 1 after 13 steps ({mode}, {block}): {err:.2e}")
+    assert err < 2e-6
+    assert torch.equal(mom, mom_ref)
+
+
+def test_four_lanes_per_node_q729_one_step_matches_oracle(torch):
+    """D3Q729, N = 5 (nine x-slabs over four lanes: 3, 2, 2, 2), one step from a perturbed state."""
+    draws = [(3.0, 45), (1.5, 70)]
+    lat, fl, doms, fields, tau = _batch(torch, draws, ab=(1, 2, 3, 5), deg=11, N=5, k=2)
+    lat.set_launch("direct", 128, 64, 4)
+    fa = lat.equilibrium(fl)
+    n = lat.n_nodes
+    fa[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=23), dtype=torch.float32, device="cuda")
+    fb = lat.new_state()
+    lat.step(fa, fb, 1)
+    lat.sync()
+    vs = O.make_velocity_set([1, 2, 3, 5], 11)
+    f0 = fa.cpu().numpy()
+    f1 = fb.cpu().numpy()
+    for i, d in enumerate(doms):
+        off, nx = lat.domain_offset[i], d["nx"]
+        model = O.Model(vs=vs, N=5, tau={k: v * d["tau_scale"] for k, v in tau.items()}, shift=(2, 0, 0))
+        dom = O.Domain(nx=nx, bc_x=1, state_in=(d["rho_in"], d["u_in"], d["theta_in"]),
+                       state_out=(d["rho_out"], d["u_out"], d["theta_out"]))
+        fo = O.step(f0[:, off:off + nx].astype(np.float64).reshape(-1, 1, 1, nx), model, dom)
+        g = f1[:, off:off + nx].reshape(fo.shape)
+        err = np.abs(g - fo).max() / np.abs(fo).max()
+        print(f"shock {i}: max scaled error {err:.2e}")
+        assert err < 1e-5, i
+
+
+def test_default_lanes_per_node(torch):
+    """Small shock contexts with FP64 contractions start with four lanes per node, others with one."""
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    assert lat.launch_settings() == {"mode": "direct", "block": 64, "lanes_per_node": 4}
+    big, _, _, _, _ = _batch(torch, [(1.5, 9000), (2.0, 9000)])
+    assert big.launch_settings() == {"mode": "direct", "block": 256, "lanes_per_node": 1}
+
+
+def test_four_lanes_per_node_rejected_where_unsupported(torch):
+    from paper_2401_11086_amd import Lattice
+    from paper_2401_11086_amd._lib import LbsmrtError
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= 4}
+    box = Lattice([1, 2, 3], 9, 4, tau, [dict(nx=8, ny=8, nz=8)], precision="fp64_contract")
+    with pytest.raises(LbsmrtError):
+        box.set_launch("direct", 64, 64, 4)
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    with pytest.raises(LbsmrtError):
+        lat.set_launch("direct", 64, 64, 3)
