@@ -110,18 +110,28 @@ __device__ __forceinline__ void zero_outflow(const LatticeConst& L, const Pull<Q
   }
 }
 
-// Fixed-order tree reduction of one value per thread; thread 0 receives the block sum.
-__device__ __forceinline__ double block_sum(double v, double* red) {
+// Fixed-order tree reduction of C values per thread over the block (blockDim.x a power of two
+// <= 256): every column in the same pass, so one ladder of barriers serves all of them.
+// red holds C * blockDim.x doubles.  Thread 0 receives the block sums in v.
+template <int C>
+__device__ __forceinline__ void block_sum_cols(double (&v)[C], double* red) {
   const int t = threadIdx.x;
-  red[t] = v;
+  const int B = blockDim.x;
+#pragma unroll
+  for (int c = 0; c < C; ++c) red[c * B + t] = v[c];
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
+  for (int s = B / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[c * B + t] += red[c * B + t + s];
+    }
     __syncthreads();
   }
-  const double out = red[0];
+  if (t == 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = red[c * B];
+  }
   __syncthreads();
-  return out;
 }
 
 // Work-items per block of the adjoint kernels (one wavefront).
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs 
   constexpr int M = n_moments(N);
   constexpr int NT = n_tau_slots(N);
   extern __shared__ double lds[];
-  __shared__ double red[256];
+  __shared__ double red[NT * kAdjBlock];
   Pull<Q1> P;
   const bool active = make_pull<Q1, LPN>(L, A, P);
   double tb[NT];
@@ -178,44 +188,61 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs 
       for (int i = 0; i < NT; ++i) tb[i] = 0.0;   // the group's dL/dtau counted once
     }
   }
+  block_sum_cols<NT>(tb, red);
+  if (threadIdx.x == 0) {
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const double s = block_sum(tb[i], red);
-    if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * NT + i] = s;
+    for (int i = 0; i < NT; ++i) partial[static_cast<size_t>(blockIdx.x) * NT + i] = tb[i];
   }
 }
 
-// Deterministic two-stage column sums of per-block partials [rows][cols].
-// Stage 1 (kReduceBlocks work-groups of 256): work-group g sums rows g, g + G, g + 2G, ... per
-// thread in a fixed order, then a fixed tree; writes stage[g][col].
+// Deterministic two-stage column sums of per-block partials [rows][cols], cols <= kTauCols.
+// Stage 1 (kReduceBlocks work-groups of 256): work-item t of group g sums rows
+// g + G t, g + G (t + 256), ... in that order for every column, then one fixed tree per
+// group; writes stage[g][col].  Stage 2 sums the G rows of stage the same way in one group.
 constexpr int kReduceBlocks = 256;
 
 __global__ __launch_bounds__(256) void k_reduce_stage1(const double* __restrict__ partial, int rows, int cols,
                                                        double* __restrict__ stage) {
-  __shared__ double red[256];
-  for (int c = 0; c < cols; ++c) {
-    double s = 0.0;
-    for (int r = blockIdx.x + gridDim.x * static_cast<int>(threadIdx.x); r < rows;
-         r += gridDim.x * static_cast<int>(blockDim.x))
-      s += partial[static_cast<size_t>(r) * cols + c];
-    const double t = block_sum(s, red);
-    if (threadIdx.x == 0) stage[static_cast<size_t>(blockIdx.x) * cols + c] = t;
+  __shared__ double red[kTauCols * 256];
+  double s[kTauCols];
+#pragma unroll
+  for (int c = 0; c < kTauCols; ++c) s[c] = 0.0;
+  for (int r = blockIdx.x + gridDim.x * static_cast<int>(threadIdx.x); r < rows;
+       r += gridDim.x * static_cast<int>(blockDim.x)) {
+#pragma unroll
+    for (int c = 0; c < kTauCols; ++c)
+      if (c < cols) s[c] += partial[static_cast<size_t>(r) * cols + c];
+  }
+  block_sum_cols<kTauCols>(s, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < kTauCols; ++c)
+      if (c < cols) stage[static_cast<size_t>(blockIdx.x) * cols + c] = s[c];
   }
 }
 
-// Stage 2 for dL/dtau: out[n*3+m] += sum_g stage[g][tau_slot(n,m)] in order.
+// Stage 2 (one group of kReduceBlocks work-items): column sums of stage[kReduceBlocks][NT].
+template <int NT>
+__device__ __forceinline__ void stage2_sums(const double* __restrict__ stage, double (&s)[NT], double* red) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) s[c] = stage[static_cast<size_t>(t) * NT + c];
+  block_sum_cols<NT>(s, red);
+}
+
+// Stage 2 for dL/dtau: out[n*3+m] += column tau_slot(n,m).  Launch: 1 x kReduceBlocks.
 template <int N>
-__global__ void k_reduce_tau(const double* __restrict__ stage, int groups, double* __restrict__ out) {
+__global__ __launch_bounds__(kReduceBlocks) void k_reduce_tau(const double* __restrict__ stage,
+                                                              double* __restrict__ out) {
   constexpr int NT = n_tau_slots(N);
-  const int c = threadIdx.x;
-  if (c >= NT) return;
-  double s = 0.0;
-  for (int g = 0; g < groups; ++g) s += stage[static_cast<size_t>(g) * NT + c];
-  int n = 2, m = 0;
-  for (int nn = 2; nn <= N; ++nn)
-    for (int mm = 0; 2 * mm <= nn; ++mm)
-      if (!(nn == 2 && mm == 1) && tau_slot(nn, mm) == c) { n = nn; m = mm; }
-  out[n * 3 + m] += s;
+  __shared__ double red[NT * kReduceBlocks];
+  double s[NT];
+  stage2_sums<NT>(stage, s, red);
+  if (threadIdx.x == 0) {
+    for (int nn = 2; nn <= N; ++nn)
+      for (int mm = 0; 2 * mm <= nn; ++mm)
+        if (!(nn == 2 && mm == 1)) out[nn * 3 + mm] += s[tau_slot(nn, mm)];
+  }
 }
 
 // Seed of the adjoint for L = sum_x [s0^2 (rho - rho*)^2 + s1^2 (theta - theta*)^2 + s2^2 (q_x - q_x*)^2]
@@ -274,18 +301,19 @@ __global__ __launch_bounds__(256) void k_loss_seed(LatticeConst L, StepArgs A, c
     if (SHOCK && P.bc_x == 1) zero_outflow<Q1>(L, P, lam, A.stride);
     (void)p;
   }
-  const double s = block_sum(ell, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  double v[1] = {ell};
+  block_sum_cols<1>(v, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
 }
 
-// Stage 2 for plain columns: out[c] (+)= sum_g stage[g][c] in order.
-__global__ void k_reduce_partials(const double* __restrict__ stage, int groups, int cols, double* __restrict__ out,
-                                  int accumulate) {
-  const int c = threadIdx.x;
-  if (c >= cols) return;
-  double s = 0.0;
-  for (int g = 0; g < groups; ++g) s += stage[static_cast<size_t>(g) * cols + c];
-  out[c] = accumulate ? out[c] + s : s;
+// Stage 2 for the loss (one column): out[0] (+)= sum over the kReduceBlocks rows of stage.
+// Launch: 1 x kReduceBlocks.
+__global__ __launch_bounds__(kReduceBlocks) void k_reduce_loss(const double* __restrict__ stage,
+                                                               double* __restrict__ out, int accumulate) {
+  __shared__ double red[kReduceBlocks];
+  double s[1];
+  stage2_sums<1>(stage, s, red);
+  if (threadIdx.x == 0) out[0] = accumulate ? out[0] + s[0] : s[0];
 }
 
 }  // namespace lbsmrt

@@ -123,7 +123,7 @@ struct Launch {
                          lam_t, c->d_partial);
     hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
                        n_tau_slots(N), c->d_stage);
-    hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(64), 0, s, c->d_stage, kReduceBlocks, A.dtau);
+    hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
   }
   static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
                         float* lam, hipStream_t s) {
@@ -561,7 +561,7 @@ lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* c, const float* f, const double* targ
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::loss_seed(c, A, f, target, scales, lam, s); });
   hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, c->n_blocks_adj, 1,
                      c->d_stage);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, c->d_stage, kReduceBlocks, 1, loss, 0);
+  hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, loss, 0);
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 
