@@ -7,15 +7,15 @@ import os
 
 import torch
 
-CANDIDATES = [(mode, block, lpn) for lpn in (1, 4) for mode in ("direct", "graph", "persistent")
+CANDIDATES = [(mode, block, lpn) for lpn in (1, 2, 4) for mode in ("direct", "graph", "persistent")
               for block in (64, 128, 256)]
 
 
 def _candidates(lat):
-    """Lanes per node 4 exists for shock contexts with FP64 contractions only."""
+    """More than one lane per node exists for shock contexts with FP64 contractions only."""
     shock = any(int(d.get("bc_x", 0)) != 0 for d in lat.domains)
-    ok4 = shock and lat.precision == "fp64_contract"
-    return [c for c in CANDIDATES if c[2] == 1 or ok4]
+    split_ok = shock and lat.precision == "fp64_contract"
+    return [c for c in CANDIDATES if c[2] == 1 or split_ok]
 
 
 def _cache_path():

@@ -27,7 +27,7 @@ struct lbsmrt_ctx {
   long long n_nodes = 0, stride = 0;
   bool shock = false;
   int block = 256;
-  int lpn = 1;                       // lanes per node of the step kernel (1, or 4: shocks, FP64)
+  int lpn = 1;                       // lanes per node of the step kernel (1; 2 or 4: shocks, FP64)
   int n_blocks = 0;
   int n_ghost = 0;
   DomainDev* d_doms = nullptr;
@@ -39,7 +39,8 @@ struct lbsmrt_ctx {
   BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
   BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
   int n_blocks_adj4 = 0;
-  bool lpn4_ok = false;              // shock domains, FP64 contractions, state below 4 GiB
+  bool lpn4_ok = false;              // lanes_per_node 2 and 4 allowed: shock domains, FP64
+                                     // contractions, state below 4 GiB
   double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
   // launch mode of lbsmrt_step
   int mode = LBSMRT_LAUNCH_DIRECT;
@@ -79,6 +80,9 @@ struct Launch {
     if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 4>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
                          A, src, dst);
+    else if (PREC == kPrecFp64 && c->shock && c->lpn == 2)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 2>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
+                         A, src, dst);
     else if (c->shock)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, PREC>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src,
                          dst);
@@ -97,6 +101,8 @@ struct Launch {
   static const void* persistent(const lbsmrt_ctx* c) {
     if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
       return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
+    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2)
+      return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 2>);
     if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
     return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
   }
@@ -464,8 +470,8 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   if (block_size != 0 && block_size != 64 && block_size != 128 && block_size != 256) return LBSMRT_E_ARG;
   if (mode == LBSMRT_LAUNCH_GRAPH && (graph_steps < 2 || graph_steps > 4096 || (graph_steps & 1)))
     return LBSMRT_E_ARG;
-  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 4) return LBSMRT_E_ARG;
-  if (lanes_per_node == 4 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
+  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4) return LBSMRT_E_ARG;
+  if (lanes_per_node > 1 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
   drop_graph(c);
   const int bs = block_size != 0 ? block_size : c->block;

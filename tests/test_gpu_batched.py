@@ -116,9 +116,10 @@ def test_batched_shock_matches_oracle_one_step(torch):
         assert np.abs(g - fo).max() / np.abs(fo).max() < 1e-5, i
 
 
-@pytest.mark.parametrize("mode,block", [("direct", 64), ("direct", 256), ("graph", 128), ("persistent", 64)])
-def test_four_lanes_per_node(torch, mode, block):
-    """lanes_per_node = 4 (each node's x-slabs split over a quad of lanes): 13 steps agree with
+@pytest.mark.parametrize("mode,block,lpn", [("direct", 64, 4), ("direct", 256, 4), ("graph", 128, 4),
+                                            ("persistent", 64, 4), ("direct", 128, 2), ("persistent", 256, 2)])
+def test_lanes_per_node(torch, mode, block, lpn):
+    """lanes_per_node = 2 or 4 (each node's x-slabs split over a group of lanes): 13 steps agree with
     lanes_per_node = 1 to float32 rounding (the FP64 projection sums run in another order), equal
     the direct launch with the same split bitwise, and leave the moment read-out unchanged."""
     lat, fl, doms, fields, tau = _batch(torch, DRAWS)
@@ -130,11 +131,11 @@ def test_four_lanes_per_node(torch, mode, block):
     ra.copy_(f0)
     ref = lat.step(ra, rb, 13)
     mom_ref = lat.moments(ref).clone()
-    lat.set_launch("direct", block, 64, 4)
+    lat.set_launch("direct", block, 64, lpn)
     da, db = lat.new_state(), lat.new_state()
     da.copy_(f0)
     direct4 = lat.step(da, db, 13)
-    lat.set_launch(mode, block, 4, 4)
+    lat.set_launch(mode, block, 4, lpn)
     fa, fb = lat.new_state(), lat.new_state()
     fa.copy_(f0)
     out = lat.step(fa, fb, 13)
@@ -142,7 +143,7 @@ def test_four_lanes_per_node(torch, mode, block):
     lat.sync()
     assert torch.equal(out[:, :n], direct4[:, :n])
     err = float((out[:, :n].double() - ref[:, :n].double()).abs().max() / ref[:, :n].double().abs().max())
-    print(f"lanes_per_node 4 vs 1 after 13 steps ({mode}, {block}): {err:.2e}")
+    print(f"lanes_per_node {lpn} vs 1 after 13 steps ({mode}, {block}): {err:.2e}")
     assert err < 2e-6
     assert torch.equal(mom, mom_ref)
 
