@@ -68,12 +68,16 @@ def recorded_traffic(workload, precision):
         return None
 
 
-def cpu_baseline(ab, deg, N, edge, kn, sample_edge=32, steps=12):
-    """The FP64 oracle on a sample_edge^3 box of the same Fourier workload
-    (same modes), `steps` steps; MLUPS scaled from that sample."""
+def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
+    """The FP64 oracle on a sample_edge^3 box of the same Fourier workload (same modes and
+    relaxation times), `steps` steps from the library's FP32 equilibrium state; MLUPS scaled
+    from that sample.  The same steps on the GPU in each contraction precision give each form's
+    error against the oracle (max |f_gpu - f_oracle| / max |f_oracle|, and the largest deviation
+    of rho and theta)."""
     import numpy as np
 
     import oracle as O
+    from paper_2401_11086_amd import Lattice
     from paper_2401_11086_amd import workloads as W
     try:
         from threadpoolctl import threadpool_info
@@ -82,19 +86,44 @@ def cpu_baseline(ab, deg, N, edge, kn, sample_edge=32, steps=12):
         threads = 1
     vs = O.make_velocity_set(ab, deg)
     tau20 = kn * edge * vs.r
-    model = O.Model(vs=vs, N=N, tau={k: v * tau20 for k, v in TAU_STAR.items() if k[0] <= N}, shift=(0, 0, 0))
+    tau = {k: v * tau20 for k, v in TAU_STAR.items() if k[0] <= N}
+    model = O.Model(vs=vs, N=N, tau=tau, shift=(0, 0, 0))
     dom = O.Domain(nx=sample_edge, ny=sample_edge, nz=sample_edge, bc_x=0)
-    fields = W.fourier_box(sample_edge)
-    f = O.equilibrium_f(fields[0], fields[1:4], fields[4], model).reshape(vs.Q, sample_edge, sample_edge, sample_edge)
+    box = [dict(nx=sample_edge, ny=sample_edge, nz=sample_edge, bc_x=0)]
+    n = sample_edge ** 3
+    fields = torch.tensor(W.fourier_box(sample_edge), dtype=torch.float64, device="cuda")
+    gpu = {}
+    f32 = None
+    for precision in ("fp64_contract", "fp32"):
+        lat = Lattice(ab, deg, N, tau, box, precision=precision)
+        fa = lat.equilibrium(fields)
+        if f32 is None:
+            f32 = fa[:, :n].cpu().numpy()
+        fb = lat.new_state()
+        cur = lat.step(fa, fb, steps)
+        lat.sync()
+        gpu[precision] = cur[:, :n].double().cpu().numpy()
+        lat.close()
+    f = f32.astype(np.float64).reshape(vs.Q, sample_edge, sample_edge, sample_edge)
     t0 = time.perf_counter()
     for _ in range(steps):
         f = O.step(f, model, dom)
     dt = time.perf_counter() - t0
     assert np.isfinite(f).all()
-    return {"value": round(sample_edge ** 3 * steps / dt / 1e6, 6), "unit": "MLUPS", "cores": threads,
+    ref = f.reshape(vs.Q, n)
+    ob_ref = O.observables(f, model, dom)
+    errors = {}
+    for precision, g in gpu.items():
+        ob = O.observables(g.reshape(f.shape), model, dom)
+        errors[precision] = {
+            "f_max_scaled": float(np.abs(g - ref).max() / np.abs(ref).max()),
+            "rho_max_abs": float(np.abs(ob["rho"] - ob_ref["rho"]).max()),
+            "theta_max_abs": float(np.abs(ob["theta"] - ob_ref["theta"]).max())}
+    return {"value": round(n * steps / dt / 1e6, 6), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample_edge}^3 periodic box of the same Fourier workload, {steps} steps, "
-                      f"{dt:.1f} s; numpy FP64 with {threads} BLAS threads"}
+                      f"{dt:.1f} s; numpy FP64 with {threads} BLAS threads",
+            "gpu_error_vs_oracle": errors}
 
 
 def copy_calibration(torch, n_floats, steps, warmup):
@@ -347,7 +376,7 @@ def main():
         out["variants"] = variants
     if not args.no_cpu_baseline:
         _progress("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(ab, deg, N, edge, args.kn)
+        out["cpu_baseline"] = cpu_baseline(torch, ab, deg, N, edge, args.kn)
     print(json.dumps(out), flush=True)
 
 
