@@ -47,7 +47,7 @@ LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull
         double s = 0.0;
 #pragma unroll
         for (int az = 0; az <= N; az += 2) s = fma(v[az], hermite_at_zero(az), s);
-        store_at(line + static_cast<size_t>(p) * stride, yoff + P.zo[p], static_cast<float>(s));
+        store_pop<!SHOCK>(line + static_cast<size_t>(p) * stride, yoff + P.zo[p], static_cast<float>(s));
       }
 #pragma unroll
       for (int j = 1; j <= p; ++j) {
@@ -57,8 +57,8 @@ LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull
           if (az & 1) o = fma(v[az], L.He64[p + j][az], o);
           else e = fma(v[az], L.He64[p + j][az], e);
         }
-        store_at(line + static_cast<size_t>(p + j) * stride, yoff + P.zo[p + j], static_cast<float>(e + o));
-        store_at(line + static_cast<size_t>(p - j) * stride, yoff + P.zo[p - j], static_cast<float>(e - o));
+        store_pop<!SHOCK>(line + static_cast<size_t>(p + j) * stride, yoff + P.zo[p + j], static_cast<float>(e + o));
+        store_pop<!SHOCK>(line + static_cast<size_t>(p - j) * stride, yoff + P.zo[p - j], static_cast<float>(e - o));
       }
     };
     {
