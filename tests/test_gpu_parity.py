@@ -318,3 +318,27 @@ def test_steady_state_driver_reaches_rankine_hugoniot_plateaus(torch):
     assert abs(m[4][0] - st["theta1"]) < 1e-2 and abs(m[4][-1] - st["theta2"]) < 1e-2
     flux = m[0] * m[1]
     assert np.abs(flux - flux.mean()).max() < 2e-3 * flux.mean()
+
+
+def test_box32_200_steps_both_precisions_match_oracle(torch):
+    """The 32^3 sub-run of the box workload (Kn = 0.05 on its own edge, 16 Fourier modes per
+    field): 200 steps of the oracle from the GPU's FP32 initial state, against 200 GPU steps in
+    each contraction precision, every moment family within 1e-4 at steps 100 and 200."""
+    case = box_case(32, D1Q7, 4, n_ref=32)
+    lats, cur = {}, {}
+    for precision in PRECISIONS:
+        lats[precision] = _lattice(case, precision)
+        cur[precision] = [_gpu_state(torch, lats[precision], case), lats[precision].new_state()]
+    fo = oracle_state_from_gpu(_host(cur["fp64_contract"][0]), case)
+    for seg in range(2):
+        for precision, lat in lats.items():
+            fa, fb = cur[precision]
+            out = lat.step(fa, fb, 100)
+            lat.sync()
+            cur[precision] = [out, fb if out is fa else fa]
+        for _ in range(100):
+            fo = O.step(fo, case["model"], case["dom"])
+        for precision, lat in lats.items():
+            errs = _compare_observables(lat, cur[precision][0], fo, case, TOL_PROFILE)
+            print(f"32^3 box, step {100 * (seg + 1)}, {precision}: worst family {max(errs, key=errs.get)} "
+                  f"{max(errs.values()):.2e}")
