@@ -360,7 +360,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        # arithmetic type of the path (the state is stored in FP32 in both precisions)
+        "dtype": "f64" if args.precision == "fp64_contract" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{edge}^3 periodic box, D3Q{lat.Q} (D1Q{lat.Q1} degree {deg}), Hermite N={N}, "
                                f"Kn={args.kn}, 16 Fourier modes per field, FP32 state, "
@@ -370,7 +371,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(args.workload, args.precision),
-                     "kernel": f"k_collide_stream<{lat.Q1},{N}>", "bytes_per_launch": bytes_per_launch},
+                     "kernel": f"k_collide_stream<{lat.Q1},{N},false,{2 if args.precision == 'fp64_contract' else 0},1>",
+                     "bytes_per_launch": bytes_per_launch},
     }
     if variants:
         out["variants"] = variants
