@@ -7,7 +7,7 @@ import os
 
 import torch
 
-CANDIDATES = [(mode, block, lpn) for lpn in (1, 2, 4) for mode in ("direct", "graph", "persistent")
+CANDIDATES = [(mode, block, lpn) for lpn in (1, 2, 4, 8) for mode in ("direct", "graph", "persistent")
               for block in (64, 128, 256)]
 
 

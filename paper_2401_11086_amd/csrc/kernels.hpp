@@ -322,11 +322,12 @@ __device__ __forceinline__ void fold_slab_project(const LatticeConst& L, const f
   }
 }
 
-// Sum over the LPN (2 or 4) consecutive lanes of a group, every lane receiving the total, by
-// DPP quad permutations (lane ^ 1, then lane ^ 2).  Floating-point addition is commutative, so
-// all lanes of a group end with bit-identical sums.
+// Sum over the LPN (2, 4 or 8) consecutive lanes of a group, every lane receiving the total, by
+// DPP permutations: lane ^ 1, lane ^ 2 (quad_perm), then the mirror within each half-row of 8
+// (after the first two steps each quad holds one value, so the mirror pairs the two quads).
+// Floating-point addition is commutative, so all lanes of a group end with bit-identical sums.
 template <int CTRL>
-__device__ __forceinline__ double dpp_quad_perm_f64(double v) {
+__device__ __forceinline__ double dpp_move_f64(double v) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
   const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
@@ -336,14 +337,19 @@ __device__ __forceinline__ double dpp_quad_perm_f64(double v) {
 
 template <int LPN, int M>
 __device__ __forceinline__ void group_allreduce(double (&a)[M]) {
-  static_assert(LPN == 2 || LPN == 4, "groups of 2 or 4 lanes");
+  static_assert(LPN == 2 || LPN == 4 || LPN == 8, "groups of 2, 4 or 8 lanes");
   constexpr int kSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
   constexpr int kSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
+  constexpr int kHalfMirror = 0x141;                            // row_half_mirror
 #pragma unroll
-  for (int i = 0; i < M; ++i) a[i] += dpp_quad_perm_f64<kSwap1>(a[i]);
-  if constexpr (LPN == 4) {
+  for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kSwap1>(a[i]);
+  if constexpr (LPN >= 4) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) a[i] += dpp_quad_perm_f64<kSwap2>(a[i]);
+    for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kSwap2>(a[i]);
+  }
+  if constexpr (LPN == 8) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kHalfMirror>(a[i]);
   }
 }
 

@@ -27,7 +27,7 @@ struct lbsmrt_ctx {
   long long n_nodes = 0, stride = 0;
   bool shock = false;
   int block = 256;
-  int lpn = 1;                       // lanes per node of the step kernel (1; 2 or 4: shocks, FP64)
+  int lpn = 1;                       // lanes per node of the step kernel (1; 2, 4 or 8: shocks, FP64)
   int n_blocks = 0;
   int n_ghost = 0;
   DomainDev* d_doms = nullptr;
@@ -38,8 +38,9 @@ struct lbsmrt_ctx {
   double* d_partial = nullptr;   // [n_blocks_adj][kTauCols] per-block partial sums
   BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
   BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
-  int n_blocks_adj4 = 0;
-  bool lpn4_ok = false;              // lanes_per_node 2 and 4 allowed: shock domains, FP64
+  BlockDev* d_blocks_adj8 = nullptr; // 8-node work-groups of the adjoint at eight lanes per node
+  int n_blocks_adj4 = 0, n_blocks_adj8 = 0;
+  bool lpn4_ok = false;              // lanes_per_node > 1 allowed: shock domains, FP64
                                      // contractions, state below 4 GiB
   double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
   // launch mode of lbsmrt_step
@@ -77,7 +78,10 @@ template <int Q1, int N>
 struct Launch {
   template <int PREC>
   static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
-    if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
+    if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 8>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
+                         A, src, dst);
+    else if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 4>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
                          A, src, dst);
     else if (PREC == kPrecFp64 && c->shock && c->lpn == 2)
@@ -99,6 +103,8 @@ struct Launch {
     return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC>);
   }
   static const void* persistent(const lbsmrt_ctx* c) {
+    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8)
+      return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 8>);
     if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
       return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
     if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2)
@@ -117,8 +123,11 @@ struct Launch {
   static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
                       hipStream_t s) {
     const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
-    const int nb = c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj;
-    if (c->shock && c->lpn == 4)
+    const int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
+    if (c->shock && c->lpn == 8)
+      hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
+                         lam_t, c->d_partial);
+    else if (c->shock && c->lpn == 4)
       hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
                          lam_t, c->d_partial);
     else if (c->shock)
@@ -188,13 +197,14 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_partial);
   (void)hipFree(c->d_blocks_adj);
   (void)hipFree(c->d_blocks_adj4);
+  (void)hipFree(c->d_blocks_adj8);
   (void)hipFree(c->d_stage);
   delete c;
 }
 
-// Contexts up to this many nodes start with four lanes per node (when eligible): with one lane
-// per node they would occupy at most a quarter of the 1024 SIMDs of the chip.
-constexpr long long kSmallContextNodes = 16384;
+// Eligible contexts start with L lanes per node while nodes * L stays within 65536 work-items
+// (1024 wavefronts, one per SIMD of the chip): 8 up to 8192 nodes, 4 up to 16384, else 1.
+constexpr long long kSplitWorkItems = 65536;
 
 // Work-group table: consecutive runs of `bs` nodes of each domain.
 std::vector<BlockDev> block_table(const std::vector<lbsmrt_domain>& doms, int bs) {
@@ -332,19 +342,23 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   c->stride = (off + 63) / 64 * 64;
   c->block = (max_local >= 4096) ? 256 : 64;
   // Shock tubes with few nodes fill a small part of the GPU, and each wavefront's serial work
-  // sets the step time: start with four lanes per node there (lbsmrt_set_launch can change it).
+  // sets the step time: start with several lanes per node there (lbsmrt_set_launch can change it).
   // (the split kernels address a slab by a 32-bit byte offset from the start of f)
   c->lpn4_ok = c->shock && c->precision == LBSMRT_FP64_CONTRACT &&
                static_cast<long long>(c->Q) * c->stride * 4 < (1LL << 32);
-  if (c->lpn4_ok && off <= kSmallContextNodes) c->lpn = 4;
+  if (c->lpn4_ok) c->lpn = off * 8 <= kSplitWorkItems ? 8 : (off * 4 <= kSplitWorkItems ? 4 : 1);
   std::vector<BlockDev> bl = block_table(c->doms, c->block / c->lpn);
   c->n_blocks = static_cast<int>(bl.size());
   std::vector<BlockDev> bla = block_table(c->doms, kAdjBlock);
   c->n_blocks_adj = static_cast<int>(bla.size());
-  std::vector<BlockDev> bla4;
-  if (c->lpn4_ok) bla4 = block_table(c->doms, kAdjBlock / 4);
+  std::vector<BlockDev> bla4, bla8;
+  if (c->lpn4_ok) {
+    bla4 = block_table(c->doms, kAdjBlock / 4);
+    bla8 = block_table(c->doms, kAdjBlock / 8);
+  }
   c->n_blocks_adj4 = static_cast<int>(bla4.size());
-  const size_t partial_rows = static_cast<size_t>(std::max(c->n_blocks_adj, c->n_blocks_adj4));
+  c->n_blocks_adj8 = static_cast<int>(bla8.size());
+  const size_t partial_rows = static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8}));
   c->n_ghost = 2 * n_domains;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -358,6 +372,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (hipMalloc(&c->d_partial, sizeof(double) * kTauCols * partial_rows) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_blocks_adj, sizeof(BlockDev) * bla.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (!bla4.empty() && hipMalloc(&c->d_blocks_adj4, sizeof(BlockDev) * bla4.size()) != hipSuccess)
+    return fail(LBSMRT_E_NOMEM);
+  if (!bla8.empty() && hipMalloc(&c->d_blocks_adj8, sizeof(BlockDev) * bla8.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_stage, sizeof(double) * kTauCols * kReduceBlocks) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
@@ -379,6 +395,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       hipMemcpyAsync(c->d_blocks_adj, bla.data(), sizeof(BlockDev) * bla.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       (!bla4.empty() && hipMemcpyAsync(c->d_blocks_adj4, bla4.data(), sizeof(BlockDev) * bla4.size(),
+                                       hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (!bla8.empty() && hipMemcpyAsync(c->d_blocks_adj8, bla8.data(), sizeof(BlockDev) * bla8.size(),
                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
       hipMemcpyAsync(c->d_ghost_fields, gf.data(), sizeof(double) * gf.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
@@ -470,7 +488,8 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   if (block_size != 0 && block_size != 64 && block_size != 128 && block_size != 256) return LBSMRT_E_ARG;
   if (mode == LBSMRT_LAUNCH_GRAPH && (graph_steps < 2 || graph_steps > 4096 || (graph_steps & 1)))
     return LBSMRT_E_ARG;
-  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4) return LBSMRT_E_ARG;
+  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4 && lanes_per_node != 8)
+    return LBSMRT_E_ARG;
   if (lanes_per_node > 1 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
   drop_graph(c);
@@ -552,7 +571,7 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* 
   if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   StepArgs A = step_args(c);
-  A.blocks = c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj;
+  A.blocks = c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj);
   A.dtau = dL_dtau;
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, s); });
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;

@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--stencil", default="d1q9", choices=["d1q7", "d1q9"])
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--max-steps", type=int, default=400000)
-    ap.add_argument("--lanes-per-node", type=int, default=0, choices=[0, 1, 2, 4],
+    ap.add_argument("--lanes-per-node", type=int, default=0, choices=[0, 1, 2, 4, 8],
                     help="lanes per node of the step kernel (0: the library's default)")
     args = ap.parse_args()
     ab, deg = {"d1q7": ([1, 2, 3], 9), "d1q9": ([1, 2, 3, 5], 11)}[args.stencil]

@@ -168,12 +168,12 @@ def test_zero_misfit_gives_zero_loss_and_gradient(torch):
 
 
 @pytest.mark.parametrize("name", ["shock_q343_n4", "shock_q729_n5"])
-def test_adjoint_four_lanes_per_node_matches_one_lane(torch, name):
-    """The adjoint step with each node's slabs split over four lanes (the default on small shock
-    contexts) against one lane per node: same lam_t up to the order of the FP64 sums, same dL/dtau."""
+@pytest.mark.parametrize("lpn", [4, 8])
+def test_adjoint_split_lanes_match_one_lane(torch, name, lpn):
+    """The adjoint step with each node's slabs split over four or eight lanes against one lane per
+    node: same lam_t up to the order of the FP64 sums, same dL/dtau."""
     case = ADJ_CASES[name]()
     lat = _lattice(case)
-    assert lat.launch_settings()["lanes_per_node"] == 4
     n = lat.n_nodes
     f_t = _state(torch, lat, case, seed=13)
     lam_next = lat.new_state()
@@ -181,17 +181,17 @@ def test_adjoint_four_lanes_per_node_matches_one_lane(torch, name):
     lam_next[:, :n] = torch.tensor(np.random.default_rng(6).standard_normal((lat.Q, n)), dtype=torch.float32,
                                    device="cuda")
     out = {}
-    for lpn in (4, 1):
-        lat.set_launch("direct", 0, 64, lpn)
+    for k in (lpn, 1):
+        lat.set_launch("direct", 0, 64, k)
         lam_t = lat.new_state()
         lam_t.zero_()
         dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
         lat.step_adjoint(f_t, lam_next, lam_t, dtau)
         lat.sync()
-        out[lpn] = (lam_t[:, :n].double().clone(), dtau.clone())
-    (l4, d4), (l1, d1) = out[4], out[1]
+        out[k] = (lam_t[:, :n].double().clone(), dtau.clone())
+    (l4, d4), (l1, d1) = out[lpn], out[1]
     err = float((l4 - l1).abs().max() / l1.abs().max())
     derr = float((d4 - d1).abs().max() / d1.abs().max())
-    print(f"{name}: lam_t {err:.2e}, dL/dtau {derr:.2e}")
+    print(f"{name}, {lpn} lanes: lam_t {err:.2e}, dL/dtau {derr:.2e}")
     assert err < 1e-6
     assert derr < 1e-10

@@ -117,9 +117,10 @@ def test_batched_shock_matches_oracle_one_step(torch):
 
 
 @pytest.mark.parametrize("mode,block,lpn", [("direct", 64, 4), ("direct", 256, 4), ("graph", 128, 4),
-                                            ("persistent", 64, 4), ("direct", 128, 2), ("persistent", 256, 2)])
+                                            ("persistent", 64, 4), ("direct", 128, 2), ("persistent", 256, 2),
+                                            ("direct", 64, 8), ("graph", 256, 8), ("persistent", 128, 8)])
 def test_lanes_per_node(torch, mode, block, lpn):
-    """lanes_per_node = 2 or 4 (each node's x-slabs split over a group of lanes): 13 steps agree with
+    """lanes_per_node = 2, 4 or 8 (each node's x-slabs split over a group of lanes): 13 steps agree with
     lanes_per_node = 1 to float32 rounding (the FP64 projection sums run in another order), equal
     the direct launch with the same split bitwise, and leave the moment read-out unchanged."""
     lat, fl, doms, fields, tau = _batch(torch, DRAWS)
@@ -148,11 +149,13 @@ def test_lanes_per_node(torch, mode, block, lpn):
     assert torch.equal(mom, mom_ref)
 
 
-def test_four_lanes_per_node_q729_one_step_matches_oracle(torch):
-    """D3Q729, N = 5 (nine x-slabs over four lanes: 3, 2, 2, 2), one step from a perturbed state."""
+@pytest.mark.parametrize("lpn", [4, 8])
+def test_split_lanes_q729_one_step_matches_oracle(torch, lpn):
+    """D3Q729, N = 5 (nine x-slabs over four lanes: 3, 2, 2, 2; over eight: 2, 1, ..., 1), one step
+    from a perturbed state."""
     draws = [(3.0, 45), (1.5, 70)]
     lat, fl, doms, fields, tau = _batch(torch, draws, ab=(1, 2, 3, 5), deg=11, N=5, k=2)
-    lat.set_launch("direct", 128, 64, 4)
+    lat.set_launch("direct", 128, 64, lpn)
     fa = lat.equilibrium(fl)
     n = lat.n_nodes
     fa[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=23), dtype=torch.float32, device="cuda")
@@ -175,9 +178,12 @@ def test_four_lanes_per_node_q729_one_step_matches_oracle(torch):
 
 
 def test_default_lanes_per_node(torch):
-    """Small shock contexts with FP64 contractions start with four lanes per node, others with one."""
+    """Shock contexts with FP64 contractions start with 8 lanes per node up to 8192 nodes, 4 up to
+    16384, then 1."""
     lat, fl, doms, fields, tau = _batch(torch, DRAWS)
-    assert lat.launch_settings() == {"mode": "direct", "block": 64, "lanes_per_node": 4}
+    assert lat.launch_settings() == {"mode": "direct", "block": 64, "lanes_per_node": 8}
+    mid, _, _, _, _ = _batch(torch, [(1.5, 6000), (2.0, 6000)])
+    assert mid.launch_settings() == {"mode": "direct", "block": 256, "lanes_per_node": 4}
     big, _, _, _, _ = _batch(torch, [(1.5, 9000), (2.0, 9000)])
     assert big.launch_settings() == {"mode": "direct", "block": 256, "lanes_per_node": 1}
 
