@@ -2,6 +2,8 @@
 seeded inputs.  Tolerances: one step from an identical FP32 state, every
 moment family within 1e-5 of its scale (max|ref| or rho_ref theta_ref^(n/2));
 multi-step trajectories within 1e-4 on normalised profiles."""
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 TOL_STEP = 1e-5
 TOL_PROFILE = 1e-4
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -342,3 +345,25 @@ def test_box32_200_steps_both_precisions_match_oracle(torch):
             errs = _compare_observables(lat, cur[precision][0], fo, case, TOL_PROFILE)
             print(f"32^3 box, step {100 * (seg + 1)}, {precision}: worst family {max(errs, key=errs.get)} "
                   f"{max(errs.values()):.2e}")
+
+
+def test_steady_profile_matches_oracle_steady_profile(torch):
+    """Ma = 1.5, D3Q343, N = 4, Nx = 48, run to a steady state on the GPU (FP32 state, FP64
+    contractions) against the oracle's steady profile in tests/golden (written by
+    make_steady_shock_profile.py from the same set-up): normalised rho, theta, q_x within 1e-4."""
+    from paper_2401_11086_amd import _lib as C
+    from paper_2401_11086_amd.steady import run_to_steady
+    ref = np.loadtxt(os.path.join(GOLDEN, "steady_shock_ma1.5_q343_n4_nx48.txt"))
+    case = shock_case(1.5, 48, D1Q7, 4)
+    lat = _lattice(case, "fp64_contract")
+    fa = _gpu_state(torch, lat, case)
+    fb = lat.new_state()
+    res, f = run_to_steady(lat, fa, fb, max_steps=100000)
+    assert res["converged"], res
+    g = _gpu_moments(lat, f, C.MOM_BASIC | C.MOM_Q)
+    gn = _normalised(g[0], g[4], g[5], case["states"])
+    dx = _crossing(gn[0]) - _crossing(ref[:, 1])
+    raw = max(float(np.abs(a - ref[:, k + 1]).max()) for k, a in enumerate(gn))
+    print(f"steady after {res['steps']} steps: shock offset {dx:+.2e} cells, max normalised difference {raw:.2e}")
+    assert abs(dx) < 1e-3
+    assert raw < TOL_PROFILE
