@@ -49,7 +49,9 @@ typedef enum {
   LBSMRT_E_STATE = 3,        /* a node left rho > 0, 0 < theta < 2, or became non-finite */
   LBSMRT_E_HIP = 4,          /* a HIP runtime call failed */
   LBSMRT_E_NOMEM = 5,        /* device or host allocation failed */
-  LBSMRT_E_UNSUPPORTED = 6   /* a (Q1, N) pair with no compiled kernel */
+  LBSMRT_E_UNSUPPORTED = 6   /* valid but not built: a (Q1, N) pair with no compiled kernel, the
+                                reserved precision, regularized = 0, or a launch setting the
+                                context does not allow */
 } lbsmrt_status;
 
 /* Arithmetic of the projection / rebuild contractions.  The state f is float32 in every mode.
