@@ -110,17 +110,6 @@ __device__ __forceinline__ bool make_pull(const LatticeConst& L, const StepArgs&
   return true;
 }
 
-// Source x of population column ix: >= 0 inside, -1 / -2 for the left / right ghost.
-template <int Q1>
-__device__ __forceinline__ int source_x(const LatticeConst& L, const Pull<Q1>& P, int ix) {
-  int xs = P.x - (L.e[ix] + L.k[0]);
-  if (P.bc_x == 0) {
-    xs %= P.nx;
-    if (xs < 0) xs += P.nx;
-    return xs;
-  }
-  return xs < 0 ? -1 : (xs >= P.nx ? -2 : xs);
-}
 
 // Row ix of a per-abscissa table.  With ix uniform across the wavefront (LPN = 1) this is a
 // plain (scalar) lookup; with ix differing between lanes it is a select over the Q1 rows, which
@@ -154,7 +143,8 @@ __device__ __forceinline__ int abscissa_of(const LatticeConst& L, int ix) {
   }
 }
 
-// source_x for a given abscissa e of the population column
+// Source x of the population column with 1D integer e: >= 0 inside, -1 / -2 for the left /
+// right ghost.  source_x takes the column index ix.
 template <int Q1>
 __device__ __forceinline__ int source_x_e(const LatticeConst& L, const Pull<Q1>& P, int e) {
   int xs = P.x - (e + L.k[0]);
@@ -164,6 +154,11 @@ __device__ __forceinline__ int source_x_e(const LatticeConst& L, const Pull<Q1>&
     return xs;
   }
   return xs < 0 ? -1 : (xs >= P.nx ? -2 : xs);
+}
+
+template <int Q1>
+__device__ __forceinline__ int source_x(const LatticeConst& L, const Pull<Q1>& P, int ix) {
+  return source_x_e<Q1>(L, P, L.e[ix]);
 }
 
 // Gather the streamed populations and project them (eq:an), sum-factorised:

@@ -144,22 +144,6 @@ __device__ __forceinline__ void irreducible_part(const double* dn, double* out) 
   for (int i = 0; i < n_sym(L); ++i) out[i] *= bnm;
 }
 
-// Piece sym(d^(n,m) delta^m), rank n, for m >= 1.
-template <int n, int m>
-__device__ __forceinline__ void irreducible_piece(const double* dn, double* P) {
-  static_assert(m >= 1, "");
-  constexpr int L = n - 2 * m;
-  double part[n_sym(L)];
-  irreducible_part<n, m>(dn, part);
-  if constexpr (m == 1) {
-    sym_delta<L>(part, P);
-  } else {
-    double tmp[n_sym(L + 2)];
-    sym_delta<L>(part, tmp);
-    sym_delta<L + 2>(tmp, P);
-  }
-}
-
 // D = a D - delta Y  (rank L -> rank L+2, in place on D)
 template <int L>
 __device__ __forceinline__ void sym_delta_update(const double* Y, double a, double* D) {
