@@ -26,10 +26,12 @@ class Lattice:
     tau: dict {(n, m): tau_nm} in time-step units at rho_ref.
     domains: list of dicts with nx, ny, nz, bc_x and, for bc_x = 1,
     rho_in, u_in, theta_in, rho_out, u_out, theta_out (lab frame).
+    precision: "fp64_contract" (default: FP64 contractions, as fast as FP32 ones on gfx950)
+    or "fp32" (FP32 contractions); the state is float32 in both.
     """
 
     def __init__(self, abscissae, degree, N, tau, domains, shift_k=(0, 0, 0), rho_ref=1.0,
-                 tau_density_scaling=True, tau_offset_half=True, precision="fp32"):
+                 tau_density_scaling=True, tau_offset_half=True, precision="fp64_contract"):
         if not torch.cuda.is_available():
             raise RuntimeError("the LB-SMRT library runs on a gfx950 GPU; no GPU is visible")
         lib = C.lib()
