@@ -126,6 +126,64 @@ def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
             "gpu_error_vs_oracle": errors}
 
 
+def shock_samples(torch):
+    """The oracle and the GPU on two shock-tube workloads of the paper's set-up (Sec. 4.2),
+    oracle steps bounded to a few seconds each: Ma 1.2, Nx 200, D3Q343, N = 4 (whole 1000-step
+    run on the GPU, 100 oracle steps) and the Ma 3, Nx 600, D3Q729, N = 5 calibration tube
+    (20 oracle steps).  MLUPS of each, on the same initial state."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2401_11086_amd import Lattice, solve_quadrature
+    from paper_2401_11086_amd.shocks import shock_domain
+    out = []
+    for Ma, nx, ab, deg, N, gpu_steps, cpu_steps in ((1.2, 200, [1, 2, 3], 9, 4, 1000, 100),
+                                                     (3.0, 600, [1, 2, 3, 5], 11, 5, 3000, 20)):
+        c_l, _ = solve_quadrature(ab, deg)
+        d, fields, st = shock_domain(Ma, nx, c_l)
+        k = int(st["k"])
+        tau = {key: v for key, v in TAU_STAR.items() if key[0] <= N}
+        lat = Lattice(ab, deg, N, tau, [d], shift_k=(k, 0, 0), precision="fp64_contract")
+        fa = lat.equilibrium(torch.tensor(fields, dtype=torch.float64, device="cuda"))
+        f0 = fa[:, :nx].double().cpu().numpy()
+        fb = lat.new_state()
+        lat.step(fa, fb, 10)
+        ms = _time_steps(torch, lambda: lat.step(fa, fb, gpu_steps), 1) / gpu_steps
+        lat.sync()
+        lanes = lat.launch_settings()["lanes_per_node"]
+        lat.close()
+        vs = O.make_velocity_set(ab, deg)
+        model = O.Model(vs=vs, N=N, tau={key: v * d["tau_scale"] for key, v in tau.items()}, shift=(k, 0, 0))
+        dom = O.Domain(nx=nx, bc_x=1, state_in=(d["rho_in"], d["u_in"], d["theta_in"]),
+                       state_out=(d["rho_out"], d["u_out"], d["theta_out"]))
+        f = f0.reshape(-1, 1, 1, nx)
+        t0 = time.perf_counter()
+        for _ in range(cpu_steps):
+            f = O.step(f, model, dom)
+        dt = time.perf_counter() - t0
+        assert np.isfinite(f).all()
+        out.append({"workload": f"Ma {Ma} shock, Nx {nx}, D3Q{vs.Q}, N={N}",
+                    "oracle_mlups": round(nx * cpu_steps / dt / 1e6, 6), "oracle_steps": cpu_steps,
+                    "gpu_mlups": round(nx / (ms / 1e3) / 1e6, 2), "gpu_steps": gpu_steps,
+                    "gpu_lanes_per_node": lanes})
+    return out
+
+
+def device_record(torch):
+    """Name, compute units and, where rocm-smi answers, the current clocks of GPU 0."""
+    import subprocess
+    props = torch.cuda.get_device_properties(0)
+    rec = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+           "compute_units": props.multi_processor_count}
+    try:
+        res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        card = next(iter(json.loads(res.stdout).values()))
+        rec["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:
+        rec["clocks"] = None
+    return rec
+
+
 def copy_calibration(torch, n_floats, steps, warmup):
     """Plain device-to-device copy of an f-sized float32 buffer: the achievable
     HBM rate for a read + write stream, and the reference for the traffic counters."""
@@ -379,6 +437,9 @@ def main():
     if not args.no_cpu_baseline:
         _progress("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(torch, ab, deg, N, edge, args.kn)
+        _progress("oracle and GPU on two shock tubes")
+        out["cpu_baseline"]["shock_samples"] = shock_samples(torch)
+    out["device"] = device_record(torch)
     print(json.dumps(out), flush=True)
 
 
