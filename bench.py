@@ -56,14 +56,15 @@ def kernel_source_digest():
 
 def recorded_traffic(workload, precision):
     """HBM bytes per launch of the step kernel from the committed FETCH_SIZE / WRITE_SIZE counter
-    summary, if it was taken on this workload and precision with the current sources; else None."""
+    summary, if it was taken on this workload and precision with the current sources; else None.
+    The summary's `- key: value` lines hold `workload`, `source_sha256` and, per precision P,
+    `traffic_bytes_per_launch[P]`."""
     try:
         with open(TRAFFIC_PROFILE) as fh:
             kv = dict(ln[2:].split(": ", 1) for ln in fh.read().splitlines() if ln.startswith("- ") and ": " in ln)
-        if (kv.get("workload") != workload or kv.get("precision") != precision
-                or kv.get("source_sha256") != kernel_source_digest()):
+        if kv.get("workload") != workload or kv.get("source_sha256") != kernel_source_digest():
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[f"traffic_bytes_per_launch[{precision}]"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -170,17 +171,23 @@ def shock_samples(torch):
 
 
 def device_record(torch):
-    """Name, compute units and, where rocm-smi answers, the current clocks of GPU 0."""
-    import subprocess
+    """Name, compute units and, where the driver exposes them, the current shader and memory
+    clock levels of GPU 0 (read from sysfs; no helper program is started)."""
+    import glob
     props = torch.cuda.get_device_properties(0)
     rec = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
-           "compute_units": props.multi_processor_count}
-    try:
-        res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
-        card = next(iter(json.loads(res.stdout).values()))
-        rec["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
-    except Exception:
-        rec["clocks"] = None
+           "compute_units": props.multi_processor_count, "clocks": None}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        try:
+            clocks = {}
+            for kind in ("sclk", "mclk"):
+                with open(os.path.join(dev, f"pp_dpm_{kind}")) as fh:
+                    cur = [ln.split(":", 1)[1].replace("*", "").strip() for ln in fh if ln.rstrip().endswith("*")]
+                clocks[kind] = cur[0] if cur else None
+            rec["clocks"] = clocks
+            break
+        except (OSError, IndexError):
+            continue
     return rec
 
 

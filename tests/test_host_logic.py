@@ -128,8 +128,8 @@ def test_bench_traffic_record_is_keyed_by_sources(tmp_path, monkeypatch):
     digest = bench.kernel_source_digest()
     assert len(digest) == 64 and digest == bench.kernel_source_digest()
     rec = tmp_path / "t.md"
-    rec.write_text("- workload: box256_q343_n4\n- precision: fp64_contract\n"
-                   f"- traffic_bytes_per_launch: 4.6e10\n- source_sha256: {digest}\n")
+    rec.write_text("- workload: box256_q343_n4\n"
+                   f"- traffic_bytes_per_launch[fp64_contract]: 4.6e10\n- source_sha256: {digest}\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(rec))
     assert bench.recorded_traffic("box256_q343_n4", "fp64_contract") == 4.6e10
     assert bench.recorded_traffic("box256_q343_n4", "fp32") is None
