@@ -8,6 +8,8 @@ constexpr int kTauCols = (kMaxN + 1) * 3;   // dL/dtau[n][m] flattened as n*3+m
 
 // Scatter of mu = P^T abar to the streaming sources: out[q][x - s_q] = sum_alpha He_alpha(c_q) abar_alpha.
 // Populations whose source was a ghost cell (shock ends) are skipped.
+// Plain (temporal) stores: the shifted chunks of neighbouring wavefronts complete each other's
+// partial cache lines in L2 (with the non-temporal hint they went out as partial-line writes).
 // LPN > 1: each lane of a node's group scatters the slabs ix = sub, sub + LPN, ... with the
 // uniform pass count of gather_project64; a lane with no slab left repeats the last one, storing
 // the values its owner stores to the same addresses in the same instruction.
@@ -47,7 +49,7 @@ LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull
         double s = 0.0;
 #pragma unroll
         for (int az = 0; az <= N; az += 2) s = fma(v[az], hermite_at_zero(az), s);
-        store_pop<!SHOCK>(line + static_cast<size_t>(p) * stride, yoff + P.zo[p], static_cast<float>(s));
+        store_at(line + static_cast<size_t>(p) * stride, yoff + P.zo[p], static_cast<float>(s));
       }
 #pragma unroll
       for (int j = 1; j <= p; ++j) {
@@ -57,8 +59,8 @@ LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull
           if (az & 1) o = fma(v[az], L.He64[p + j][az], o);
           else e = fma(v[az], L.He64[p + j][az], e);
         }
-        store_pop<!SHOCK>(line + static_cast<size_t>(p + j) * stride, yoff + P.zo[p + j], static_cast<float>(e + o));
-        store_pop<!SHOCK>(line + static_cast<size_t>(p - j) * stride, yoff + P.zo[p - j], static_cast<float>(e - o));
+        store_at(line + static_cast<size_t>(p + j) * stride, yoff + P.zo[p + j], static_cast<float>(e + o));
+        store_at(line + static_cast<size_t>(p - j) * stride, yoff + P.zo[p - j], static_cast<float>(e - o));
       }
     };
     {
@@ -134,37 +136,41 @@ __device__ __forceinline__ void block_sum_cols(double (&v)[C], double* red) {
   __syncthreads();
 }
 
-// Work-items per block of the adjoint kernels (one wavefront).
+// Work-items per block of the adjoint kernels: one wavefront, or (periodic domains, N <= 4)
+// kAdjRowBlock, so that a work-group scatters whole 256-node rows and its shifted stores cover
+// whole cache lines.
 constexpr int kAdjBlock = 64;
+constexpr int kAdjRowBlock = 256;
 
-// Per-thread vector of M doubles in dynamic LDS, strided by the block size (conflict-free); the
-// stride is a compile-time constant so that every element address is the thread's base plus an
-// immediate offset.
+// Per-thread vector of M doubles in dynamic LDS, strided by the block size B (conflict-free);
+// the stride is a compile-time constant so that every element address is the thread's base plus
+// an immediate offset.
+template <int B>
 struct LdsVec {
   double* base;
-  __device__ __forceinline__ double operator()(int i) const { return base[i * kAdjBlock]; }
-  __device__ __forceinline__ void set(int i, double v) const { base[i * kAdjBlock] = v; }
+  __device__ __forceinline__ double operator()(int i) const { return base[i * B]; }
+  __device__ __forceinline__ void set(int i, double v) const { base[i * B] = v; }
 };
 
 // One adjoint step: lam_t = (d f_{t+1} / d f_t)^T lam_next, per-block partials of dL/dtau.
 // Dynamic LDS: 2 M doubles per work-item (the local moments d and z = Lambda d'); blocks of
 // kAdjBlock work-items.
-template <int Q1, int N, bool SHOCK, int LPN = 1>
-__global__ __launch_bounds__(kAdjBlock) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
+template <int Q1, int N, bool SHOCK, int LPN = 1, int B = kAdjBlock>
+__global__ __launch_bounds__(B) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
                                                  const float* __restrict__ lam_next, float* __restrict__ lam_t,
                                                  double* __restrict__ partial) {
   constexpr int M = n_moments(N);
   constexpr int NT = n_tau_slots(N);
   extern __shared__ double lds[];
-  __shared__ double red[NT * kAdjBlock];
+  __shared__ double red[NT * B];
   Pull<Q1> P;
   const bool active = make_pull<Q1, LPN>(L, A, P);
   double tb[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) tb[i] = 0.0;
   if (active) {
-    const LdsVec dv{lds + threadIdx.x};
-    const LdsVec zv{lds + M * kAdjBlock + threadIdx.x};
+    const LdsVec<B> dv{lds + threadIdx.x};
+    const LdsVec<B> zv{lds + M * B + threadIdx.x};
     Macro mac;
     {
       double d[M];

@@ -40,6 +40,8 @@ struct lbsmrt_ctx {
   BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
   BlockDev* d_blocks_adj8 = nullptr; // 8-node work-groups of the adjoint at eight lanes per node
   int n_blocks_adj4 = 0, n_blocks_adj8 = 0;
+  BlockDev* d_blocks_adjR = nullptr; // 256-node work-groups of the adjoint on periodic domains
+  int n_blocks_adjR = 0;             // (0: not used)
   bool lpn4_ok = false;              // lanes_per_node > 1 allowed: shock domains, FP64
                                      // contractions, state below 4 GiB
   double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
@@ -123,7 +125,19 @@ struct Launch {
   static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
                       hipStream_t s) {
     const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
-    const int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
+    int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
+    if constexpr (N <= 4) {
+      if (!c->shock && c->n_blocks_adjR > 0) {
+        nb = c->n_blocks_adjR;
+        hipLaunchKernelGGL((k_adjoint<Q1, N, false, 1, kAdjRowBlock>), dim3(nb), dim3(kAdjRowBlock),
+                           2 * sizeof(double) * n_moments(N) * kAdjRowBlock, s, c->L, A, f_t, lam_next, lam_t,
+                           c->d_partial);
+        hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
+                           n_tau_slots(N), c->d_stage);
+        hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
+        return;
+      }
+    }
     if (c->shock && c->lpn == 8)
       hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
                          lam_t, c->d_partial);
@@ -139,6 +153,15 @@ struct Launch {
     hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
                        n_tau_slots(N), c->d_stage);
     hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
+  }
+  // Raise the dynamic LDS limit of the 256-node periodic adjoint (N <= 4); false if refused.
+  static bool allow_row_adjoint() {
+    if constexpr (N <= 4) {
+      const int bytes = static_cast<int>(2 * sizeof(double) * n_moments(N) * kAdjRowBlock);
+      return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint<Q1, N, false, 1, kAdjRowBlock>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    }
+    return false;
   }
   static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
                         float* lam, hipStream_t s) {
@@ -198,6 +221,7 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_blocks_adj);
   (void)hipFree(c->d_blocks_adj4);
   (void)hipFree(c->d_blocks_adj8);
+  (void)hipFree(c->d_blocks_adjR);
   (void)hipFree(c->d_stage);
   delete c;
 }
@@ -358,7 +382,22 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   }
   c->n_blocks_adj4 = static_cast<int>(bla4.size());
   c->n_blocks_adj8 = static_cast<int>(bla8.size());
-  const size_t partial_rows = static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8}));
+  // periodic domains with N <= 4: 256-node adjoint work-groups when their LDS fits one work-group
+  std::vector<BlockDev> blaR;
+  if (!c->shock && c->N <= 4) {
+    int dev = 0, max_lds = 0;
+    const size_t need = 2 * sizeof(double) * c->M * kAdjRowBlock + sizeof(double) * n_tau_slots(c->N) * kAdjRowBlock;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        need <= static_cast<size_t>(max_lds)) {
+      bool ok = true;
+      dispatch(c->Q1, c->N, [&](auto l) { ok = decltype(l)::allow_row_adjoint(); });
+      if (ok) blaR = block_table(c->doms, kAdjRowBlock);
+    }
+  }
+  c->n_blocks_adjR = static_cast<int>(blaR.size());
+  const size_t partial_rows =
+      static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8, c->n_blocks_adjR}));
   c->n_ghost = 2 * n_domains;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -374,6 +413,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (!bla4.empty() && hipMalloc(&c->d_blocks_adj4, sizeof(BlockDev) * bla4.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
   if (!bla8.empty() && hipMalloc(&c->d_blocks_adj8, sizeof(BlockDev) * bla8.size()) != hipSuccess)
+    return fail(LBSMRT_E_NOMEM);
+  if (!blaR.empty() && hipMalloc(&c->d_blocks_adjR, sizeof(BlockDev) * blaR.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_stage, sizeof(double) * kTauCols * kReduceBlocks) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
@@ -397,6 +438,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       (!bla4.empty() && hipMemcpyAsync(c->d_blocks_adj4, bla4.data(), sizeof(BlockDev) * bla4.size(),
                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
       (!bla8.empty() && hipMemcpyAsync(c->d_blocks_adj8, bla8.data(), sizeof(BlockDev) * bla8.size(),
+                                       hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (!blaR.empty() && hipMemcpyAsync(c->d_blocks_adjR, blaR.data(), sizeof(BlockDev) * blaR.size(),
                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
       hipMemcpyAsync(c->d_ghost_fields, gf.data(), sizeof(double) * gf.size(), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
@@ -572,6 +615,7 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   StepArgs A = step_args(c);
   A.blocks = c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj);
+  if (!c->shock && c->n_blocks_adjR > 0) A.blocks = c->d_blocks_adjR;
   A.dtau = dL_dtau;
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, s); });
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
