@@ -197,6 +197,44 @@ lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* ctx, const float* f, const double* ta
  * enqueued afterwards.  E_ARG if an entry is not positive and finite. */
 lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* ctx, const double* tau);
 
+/* ---- moment-state form ---------------------------------------------------
+ * With the regularised rebuild (eq:fi) the post-collision populations of a node are
+ * f*_i = w_i sum_alpha a'_alpha He_alpha(c_i)/alpha!, fixed by its M moments a'.  A context
+ * can therefore hold its state as the moments instead: m is float32 [M][f_stride] (moment
+ * order of lbsmrt_moments' LBSMRT_MOM_ALAB rows: by order n, then a, then b descending).
+ * lbsmrt_step_moment_state advances it by the same step as lbsmrt_step (pull stream, eq:an
+ * projection, SMRT collision), written as a separable convolution of the moment fields
+ * along z, y and x; the state moves M floats per node instead of Q.  Results agree with
+ * lbsmrt_step on the expanded state up to float32 rounding of m instead of f. */
+
+/* Sizes of the moment-state buffers in floats: m_len = M * f_stride (one state) and
+ * work_len (scratch of lbsmrt_step_moment_state, 2 (N+1)^2 (N+2)/2 rows of f_stride).
+ * Either pointer may be NULL.  E_ARG for a NULL ctx. */
+lbsmrt_status lbsmrt_moment_state_len(const lbsmrt_ctx* ctx, long long* m_len, long long* work_len);
+
+/* Moments a^eq of the truncated Maxwellian (as lbsmrt_equilibrium) written to m.
+ * fields: float64 [5][n_nodes] device rows; m: [M][f_stride] float32.  Any context.  Asynchronous. */
+lbsmrt_status lbsmrt_equilibrium_moments(lbsmrt_ctx* ctx, const double* fields, float* m, void* stream);
+
+/* Own-node projection m_alpha = sum_i f_i He_alpha(c_i) (eq:an without the stream; FP64
+ * sums, stored as float32).  For a post-collision state this recovers a'.  Any context;
+ * f and m must not overlap.  Asynchronous. */
+lbsmrt_status lbsmrt_project_state(lbsmrt_ctx* ctx, const float* f, float* m, void* stream);
+
+/* Rebuild f_i = w_i sum_alpha m_alpha He_alpha(c_i)/alpha! (eq:fi) for every node, giving
+ * the population state that lbsmrt_step, lbsmrt_moments and lbsmrt_step_adjoint take.
+ * Any context; f and m must not overlap.  Asynchronous. */
+lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* ctx, const float* m, float* f, void* stream);
+
+/* Advance a moment state n_steps >= 1 steps; buffers alternate as in lbsmrt_step (result in
+ * m_a for even n_steps, in m_b for odd).  work: lbsmrt_moment_state_len's work_len floats of
+ * caller-owned device memory, contents irrelevant; none of m_a, m_b, work may overlap.
+ * E_UNSUPPORTED unless the context has exactly one periodic domain (bc_x = 0) and the
+ * stencil is D1Q7 {0, +-1, +-2, +-3} or D1Q9 {0, +-1, +-2, +-3, +-5}.  Validity failures
+ * latch the flag read by lbsmrt_sync_status.  Asynchronous. */
+lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* ctx, float* m_a, float* m_b, float* work, int n_steps,
+                                       void* stream);
+
 /* Wait for `stream` and report (and clear) the latched device state flag. */
 lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* ctx, void* stream);
 

@@ -12,6 +12,7 @@
 #include "adjoint_kernels.hpp"
 #include "kernels.hpp"
 #include "lbsmrt.h"
+#include "moment_state.hpp"
 
 using namespace lbsmrt;
 
@@ -54,6 +55,10 @@ struct lbsmrt_ctx {
   int graph_pairs = 0;
   int n_blocks_adj = 0;
   int precision = LBSMRT_FP32;
+  // moment-state form: one periodic domain and a stencil with compile-time taps
+  bool ms_ok = false;
+  MomentTaps32 ms_k32{};
+  MomentTaps64 ms_k64{};
 };
 
 namespace {
@@ -172,6 +177,36 @@ struct Launch {
       hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
                          c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
   }
+  // moment-state form: line chunk of the z and y passes (a multiple of the tap window)
+  static constexpr int kMsChunk = 4 * (2 * Taps1D<Q1>::H + 1);
+  static void ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, float* dst, float* t1, float* t2,
+                      hipStream_t s) {
+    const unsigned gx = static_cast<unsigned>((G.nx + 255) / 256);
+    hipLaunchKernelGGL((k_ms_pass_z<Q1, N, kMsChunk>), dim3(gx, G.ny, (G.nz + kMsChunk - 1) / kMsChunk), dim3(256), 0,
+                       s, c->ms_k32, G, src, t1);
+    hipLaunchKernelGGL((k_ms_pass_y<Q1, N, kMsChunk>), dim3(gx, G.nz, (G.ny + kMsChunk - 1) / kMsChunk), dim3(256), 0,
+                       s, c->ms_k32, G, t1, t2);
+    hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3(gx, G.ny, G.nz), dim3(256), 0, s, c->L, c->ms_k64, G, t2,
+                       dst);
+  }
+  static bool ms_taps_match(const lbsmrt_ctx* c) {
+    const int p = Q1 / 2;
+    for (int t = 0; t <= Taps1D<Q1>::p; ++t)
+      if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
+    return true;
+  }
+  static void ms_project(lbsmrt_ctx* c, const float* f, float* m, hipStream_t s) {
+    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+    hipLaunchKernelGGL((k_ms_project<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, f, m, c->stride, c->n_nodes);
+  }
+  static void ms_expand(lbsmrt_ctx* c, const float* m, float* f, hipStream_t s) {
+    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+    hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
+  }
+  static void ms_equilibrium(lbsmrt_ctx* c, const double* fields, float* m, hipStream_t s) {
+    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+    hipLaunchKernelGGL((k_ms_equilibrium<N>), dim3(nb), dim3(256), 0, s, c->L, fields, c->n_nodes, m, c->stride);
+  }
   static void equilibrium(lbsmrt_ctx* c, const double* fields, long long count, float* f, long long stride,
                           hipStream_t s) {
     const int bs = 256;
@@ -238,6 +273,12 @@ std::vector<BlockDev> block_table(const std::vector<lbsmrt_domain>& doms, int bs
     for (long long first = 0; first < n; first += bs) bl.push_back(BlockDev{static_cast<int>(i), static_cast<int>(first)});
   }
   return bl;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
 }
 
 lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
@@ -399,6 +440,17 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   const size_t partial_rows =
       static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8, c->n_blocks_adjR}));
   c->n_ghost = 2 * n_domains;
+  // moment-state form (lbsmrt_step_moment_state): K[t][b][a] = He_b(c_t) w_t He_a(c_t)/a! at the
+  // non-negative taps t of the stencil
+  dispatch(c->Q1, c->N, [&](auto l) { c->ms_ok = decltype(l)::ms_taps_match(c); });
+  c->ms_ok = c->ms_ok && n_domains == 1 && domains[0].bc_x == 0;
+  for (int t = 0; t <= p; ++t)
+    for (int b = 0; b <= c->N; ++b)
+      for (int a = 0; a <= c->N; ++a) {
+        const double k = L.He64[p + t][b] * L.Rw64[p + t][a];
+        c->ms_k64.K[t][b][a] = k;
+        c->ms_k32.K[t][b][a] = static_cast<float>(k);
+      }
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return LBSMRT_E_HIP; }
@@ -647,6 +699,65 @@ lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* c, const double* tau) {
       if (!(n == 2 && m == 1)) c->L.tau[n][m] = tau[n * 3 + m];
   drop_graph(c);   // captured launches hold the old relaxation times
   return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_moment_state_len(const lbsmrt_ctx* c, long long* m_len, long long* work_len) {
+  if (!c) return LBSMRT_E_ARG;
+  if (m_len) *m_len = static_cast<long long>(c->M) * c->stride;
+  if (work_len) *work_len = 2LL * n_sym(c->N) * (c->N + 1) * c->stride;
+  return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_equilibrium_moments(lbsmrt_ctx* c, const double* fields, float* m, void* stream) {
+  if (!c || !fields || !m) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_equilibrium(c, fields, m, s); });
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_project_state(lbsmrt_ctx* c, const float* f, float* m, void* stream) {
+  if (!c || !f || !m) return LBSMRT_E_ARG;
+  const size_t fb = sizeof(float) * c->Q * c->stride, mb = sizeof(float) * c->M * c->stride;
+  if (overlap(f, fb, m, mb)) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_project(c, f, m, s); });
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* c, const float* m, float* f, void* stream) {
+  if (!c || !f || !m) return LBSMRT_E_ARG;
+  const size_t fb = sizeof(float) * c->Q * c->stride, mb = sizeof(float) * c->M * c->stride;
+  if (overlap(f, fb, m, mb)) return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_expand(c, m, f, s); });
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
+lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* c, float* m_a, float* m_b, float* work, int n_steps,
+                                       void* stream) {
+  if (!c || !m_a || !m_b || !work || n_steps < 1) return LBSMRT_E_ARG;
+  if (!c->ms_ok) return LBSMRT_E_UNSUPPORTED;
+  const size_t mb = sizeof(float) * c->M * c->stride;
+  const size_t half = static_cast<size_t>(n_sym(c->N)) * (c->N + 1) * c->stride;   // floats per intermediate
+  if (overlap(m_a, mb, m_b, mb) || overlap(m_a, mb, work, 2 * half * sizeof(float)) ||
+      overlap(m_b, mb, work, 2 * half * sizeof(float)))
+    return LBSMRT_E_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const lbsmrt_domain& D = c->doms[0];
+  MsGeom G;
+  G.nx = D.nx; G.ny = D.ny; G.nz = D.nz;
+  for (int k = 0; k < 3; ++k) G.k[k] = c->L.k[k];
+  G.stride = c->stride;
+  G.tsc = D.tau_scale > 0.0 ? D.tau_scale : 1.0;
+  G.err = c->d_err;
+  float* t1 = work;
+  float* t2 = work + half;
+  for (int t = 0; t < n_steps; ++t) {
+    const float* src = (t & 1) ? m_b : m_a;
+    float* dst = (t & 1) ? m_a : m_b;
+    dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_step(c, G, src, dst, t1, t2, s); });
+  }
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 
 lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* c, void* stream) {

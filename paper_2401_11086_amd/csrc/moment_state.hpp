@@ -1,0 +1,298 @@
+// Moment-state form of the periodic LB-SMRT step (gfx950 kernels).
+//
+// With the regularised rebuild (eq:fi) the post-collision populations are fully determined by
+// the M moments a'_alpha of each node: f*_i(x) = w_i sum_alpha a'_alpha(x) He_alpha(c_i) / alpha!.
+// The pull stream followed by the projection (eq:an) is then a linear map of the moment fields,
+//   a_beta(x) = sum_alpha sum_e prod_k K_{beta_k alpha_k}(e_k) a'_alpha(x - e - k),
+//   K_{b a}(e) = He_b(c_e) w_e He_a(c_e) / a!      (1D tap of the tensor-product stencil),
+// a separable convolution that is applied one axis at a time:
+//   pass z:  a'[ax, ay, az]       -> t1[ax, ay, bz]   (P2 (N+1) fields)
+//   pass y:  t1[ax, ay, bz]       -> t2[ax, by, bz]   ((N+1) P2 fields)
+//   pass x:  t2[ax, by, bz]       -> a[bx, by, bz]    (M fields), then the SMRT collision of
+//            Sec. 3 (frame shift, irreducible split, relaxation, shift back) and the store of a'.
+// The state is float32 [M][stride] (moment index as in smrt_node.hpp); the two intermediates are
+// float32 [P2 (N+1)][stride] each.  Every node of one periodic domain (x fastest).
+//
+// Passes z and y march each work-item along its line with a register ring of the last W rows
+// (W = 2 max|e| + 1), so every input row is read once per line chunk of T rows; the taps are
+// folded over +-e (K(-e) = (-1)^(a+b) K(e)).  Pass x reads its row's shifted neighbours directly
+// (same cache lines as the row itself) and accumulates in FP64 for the collision.
+#pragma once
+#include "kernels.hpp"
+
+namespace lbsmrt {
+
+// Compile-time non-negative taps of the two stencils with a moment-state kernel:
+// D1Q7 {0, +-1, +-2, +-3} and D1Q9 {0, +-1, +-2, +-3, +-5} (Sec. 4.2).
+template <int Q1>
+struct Taps1D;
+template <>
+struct Taps1D<7> {
+  static constexpr int p = 3;
+  static constexpr int H = 3;   // max |e|
+  static constexpr int e[4] = {0, 1, 2, 3};
+};
+template <>
+struct Taps1D<9> {
+  static constexpr int p = 4;
+  static constexpr int H = 5;
+  static constexpr int e[5] = {0, 1, 2, 3, 5};
+};
+
+// K[t][b][a] = He_b(c) w He_a(c) / a! at the non-negative tap t (c = r e_t).
+struct MomentTaps32 {
+  float K[kMaxQ1 / 2 + 1][kMaxN + 1][kMaxN + 1];
+};
+struct MomentTaps64 {
+  double K[kMaxQ1 / 2 + 1][kMaxN + 1][kMaxN + 1];
+};
+
+struct MsGeom {
+  int nx, ny, nz;
+  int k[3];            // frame shift (integer), the pull source is x - e - k
+  long long stride;    // row stride of every [fields][stride] buffer
+  double tsc;          // tau scale of the domain
+  int* err;            // validity flag (kErrState)
+};
+
+// March of one line: outputs at positions p0 .. p0 + T - 1 (< len) of the line whose position q
+// has byte offset base + q * step.  Inputs: fields fin[a], a < nf (the 1D index a of the
+// convolved axis); outputs: fields fout[b], b < no (1D index b).
+template <int Q1, int N, int T>
+__device__ __forceinline__ void march_line(const MomentTaps32& K, const float* __restrict__ in,
+                                           float* __restrict__ out, long long stride, const int (&fin)[N + 1],
+                                           int nf, const int (&fout)[N + 1], int no, unsigned base, unsigned step,
+                                           int len, int p0, int kshift) {
+  using S = Taps1D<Q1>;
+  constexpr int H = S::H;
+  constexpr int W = 2 * H + 1;
+  static_assert(T % W == 0, "chunk length must be a multiple of the window");
+  const float* __restrict__ src[N + 1];
+#pragma unroll
+  for (int a = 0; a <= N; ++a) src[a] = in + static_cast<size_t>(a < nf ? fin[a] : fin[0]) * stride;
+  // ring slot r % W holds line position p0 - H - kshift + r (mod len)
+  int q = (p0 - H - kshift) % len;
+  if (q < 0) q += len;
+  float ring[W][N + 1];
+#pragma unroll
+  for (int r = 0; r < W - 1; ++r) {
+    const unsigned off = base + static_cast<unsigned>(q) * step;
+#pragma unroll
+    for (int a = 0; a <= N; ++a)
+      if (a < nf) ring[r][a] = load_at(src[a], off);
+    q = (q + 1 == len) ? 0 : q + 1;
+  }
+#pragma unroll 1
+  for (int jb = 0; jb < T; jb += W) {
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+      {
+        const unsigned off = base + static_cast<unsigned>(q) * step;
+#pragma unroll
+        for (int a = 0; a <= N; ++a)
+          if (a < nf) ring[(jj + W - 1) % W][a] = load_at(src[a], off);
+        q = (q + 1 == len) ? 0 : q + 1;
+      }
+      const int pos = p0 + jb + jj;
+      if (pos < len) {
+        float acc[N + 1];
+#pragma unroll
+        for (int b = 0; b <= N; ++b) acc[b] = 0.f;
+#pragma unroll
+        for (int a = 0; a <= N; ++a) {
+          if (a >= nf) continue;
+          // the tap e pulls line position pos - e - kshift = ring slot (jj + H - e) % W
+          if (!(a & 1)) {
+            const float c = ring[(jj + H) % W][a];
+#pragma unroll
+            for (int b = 0; b <= N; b += 2) acc[b] = fmaf(K.K[0][b][a], c, acc[b]);
+          }
+#pragma unroll
+          for (int t = 1; t <= S::p; ++t) {
+            const float vp = ring[(jj + H - S::e[t]) % W][a];
+            const float vm = ring[(jj + H + S::e[t]) % W][a];
+            const float s = vp + vm, d = vp - vm;
+#pragma unroll
+            for (int b = 0; b <= N; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? d : s, acc[b]);
+          }
+        }
+        const unsigned off = base + static_cast<unsigned>(pos) * step;
+#pragma unroll
+        for (int b = 0; b <= N; ++b)
+          if (b < no) store_at(out + static_cast<size_t>(fout[b]) * stride, off, acc[b]);
+      }
+    }
+  }
+}
+
+// Pass z: a'[ax, ay, az] -> t1[pair(ax, ay) (N+1) + bz].  Grid (ceil(nx/256), ny, ceil(nz/T)).
+template <int Q1, int N, int T>
+__global__ __launch_bounds__(256) void k_ms_pass_z(MomentTaps32 K, MsGeom G, const float* __restrict__ m,
+                                                   float* __restrict__ t1) {
+  const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (x >= G.nx) return;
+  const int y = static_cast<int>(blockIdx.y);
+  const int z0 = static_cast<int>(blockIdx.z) * T;
+  const unsigned base = static_cast<unsigned>(x + G.nx * y) * 4u;
+  const unsigned step = static_cast<unsigned>(G.nx * G.ny) * 4u;
+#pragma unroll 1
+  for (int ax = 0; ax <= N; ++ax)
+#pragma unroll 1
+    for (int ay = 0; ax + ay <= N; ++ay) {
+      int fin[N + 1], fout[N + 1];
+#pragma unroll
+      for (int a = 0; a <= N; ++a) fin[a] = midx(ax, ay, a <= N - ax - ay ? a : 0);
+#pragma unroll
+      for (int b = 0; b <= N; ++b) fout[b] = pair_pos(ax, ay) * (N + 1) + b;
+      march_line<Q1, N, T>(K, m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, G.k[2]);
+    }
+}
+
+// Pass y: t1[pair(ax, ay) (N+1) + bz] -> t2[ax P2 + pair(by, bz)].  Grid (ceil(nx/256), nz, ceil(ny/T)).
+template <int Q1, int N, int T>
+__global__ __launch_bounds__(256) void k_ms_pass_y(MomentTaps32 K, MsGeom G, const float* __restrict__ t1,
+                                                   float* __restrict__ t2) {
+  constexpr int P2 = n_sym(N);
+  const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (x >= G.nx) return;
+  const int z = static_cast<int>(blockIdx.y);
+  const int y0 = static_cast<int>(blockIdx.z) * T;
+  const unsigned base = static_cast<unsigned>(x + G.nx * G.ny * z) * 4u;
+  const unsigned step = static_cast<unsigned>(G.nx) * 4u;
+#pragma unroll 1
+  for (int ax = 0; ax <= N; ++ax)
+#pragma unroll 1
+    for (int bz = 0; bz <= N; ++bz) {
+      int fin[N + 1], fout[N + 1];
+#pragma unroll
+      for (int a = 0; a <= N; ++a) fin[a] = pair_pos(ax, a <= N - ax ? a : 0) * (N + 1) + bz;
+#pragma unroll
+      for (int b = 0; b <= N; ++b) fout[b] = ax * P2 + pair_pos(b <= N - bz ? b : 0, bz);
+      march_line<Q1, N, T>(K, t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, G.k[1]);
+    }
+}
+
+// Pass x + collision: t2[ax P2 + pair(by, bz)] -> a[bx, by, bz] (FP64), SMRT collision, store a'.
+// Grid (ceil(nx/256), ny, nz).
+template <int Q1, int N>
+__global__ __launch_bounds__(256) void k_ms_pass_x_collide(LatticeConst L, MomentTaps64 K, MsGeom G,
+                                                           const float* __restrict__ t2, float* __restrict__ m_out) {
+  using S = Taps1D<Q1>;
+  constexpr int M = n_moments(N);
+  constexpr int P2 = n_sym(N);
+  const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (x >= G.nx) return;
+  const int y = static_cast<int>(blockIdx.y);
+  const int z = static_cast<int>(blockIdx.z);
+  const int row = G.nx * (y + G.ny * z);
+  // byte offsets of the sources x - e - k_x (tap +e) and x + e - k_x (tap -e)
+  unsigned op[S::p + 1], om[S::p + 1];
+#pragma unroll
+  for (int t = 0; t <= S::p; ++t) {
+    int sp = (x - S::e[t] - G.k[0]) % G.nx;
+    int sm = (x + S::e[t] - G.k[0]) % G.nx;
+    sp += sp < 0 ? G.nx : 0;
+    sm += sm < 0 ? G.nx : 0;
+    op[t] = static_cast<unsigned>(row + sp) * 4u;
+    om[t] = static_cast<unsigned>(row + sm) * 4u;
+  }
+  double d[M];
+#pragma unroll
+  for (int by = 0; by <= N; ++by)
+#pragma unroll
+    for (int bz = 0; bz <= N; ++bz) {
+      if (by + bz > N) continue;
+      double acc[N + 1];
+#pragma unroll
+      for (int b = 0; b <= N; ++b) acc[b] = 0.0;
+#pragma unroll
+      for (int a = 0; a <= N; ++a) {
+        const float* __restrict__ src = t2 + static_cast<size_t>(a * P2 + pair_pos(by, bz)) * G.stride;
+        if (!(a & 1)) {
+          const double c = static_cast<double>(load_at(src, op[0]));
+#pragma unroll
+          for (int b = 0; b <= N; b += 2) acc[b] = fma(K.K[0][b][a], c, acc[b]);
+        }
+#pragma unroll
+        for (int t = 1; t <= S::p; ++t) {
+          const double vp = static_cast<double>(load_at(src, op[t]));
+          const double vm = static_cast<double>(load_at(src, om[t]));
+          const double s = vp + vm, dd = vp - vm;
+#pragma unroll
+          for (int b = 0; b <= N; ++b) acc[b] = fma(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
+        }
+      }
+      // Finish each group before the next one's loads: the empty asm statements pin the sums
+      // here and order the loads, otherwise every loaded value stays live until the collision.
+#pragma unroll
+      for (int bx = 0; bx <= N; ++bx)
+        if (bx + by + bz <= N) {
+          asm volatile("" : "+v"(acc[bx]));
+          d[midx(bx, by, bz)] = acc[bx];
+        }
+      asm volatile("" ::: "memory");
+    }
+  double S5[5];
+  sums_from_a<N>(d, L, S5);
+  Macro mac = macro_from_sums(L, S5, G.err);
+  mac.tsc = G.tsc;
+  to_local<N>(d, mac);
+  relax<N>(d, L, mac.rho, mac.tsc);
+  to_lattice<N>(d, mac);
+  const unsigned off = static_cast<unsigned>(row + x) * 4u;
+#pragma unroll
+  for (int i = 0; i < M; ++i) store_at(m_out + static_cast<size_t>(i) * G.stride, off, static_cast<float>(d[i]));
+}
+
+// Own-node projection of a population state: m[alpha] = sum_i f_i He_alpha(c_i) (FP64 sums).
+template <int Q1, int N>
+__global__ __launch_bounds__(256) void k_ms_project(LatticeConst L, const float* __restrict__ f,
+                                                    float* __restrict__ m, long long stride, long long count) {
+  constexpr int M = n_moments(N);
+  const long long node = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (node >= count) return;
+  double a[M];
+  own_project64<Q1, N, false>(L, f, stride, static_cast<int>(node), a);
+#pragma unroll
+  for (int i = 0; i < M; ++i) m[static_cast<size_t>(i) * stride + node] = static_cast<float>(a[i]);
+}
+
+// Rebuild of the populations from a moment state: f_i = w_i sum_alpha m_alpha He_alpha(c_i) / alpha!.
+template <int Q1, int N>
+__global__ __launch_bounds__(256) void k_ms_expand(LatticeConst L, const float* __restrict__ m,
+                                                   float* __restrict__ f, long long stride, long long count) {
+  constexpr int M = n_moments(N);
+  const long long node = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (node >= count) return;
+  double a[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) a[i] = static_cast<double>(m[static_cast<size_t>(i) * stride + node]);
+  reconstruct_store64<Q1, N>(L, a, f, stride, static_cast<int>(node));
+}
+
+// Moments of the truncated Maxwellian (App. B closed form per axis) of lab-frame (rho, u, theta).
+template <int N>
+__global__ __launch_bounds__(256) void k_ms_equilibrium(LatticeConst L, const double* __restrict__ fields,
+                                                        long long count, float* __restrict__ m, long long stride) {
+  const long long node = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (node >= count) return;
+  const double rho = fields[node];
+  const double ux = fields[count + node] - L.r * L.k[0];
+  const double uy = fields[2 * count + node] - L.r * L.k[1];
+  const double uz = fields[3 * count + node] - L.r * L.k[2];
+  const double th = fields[4 * count + node];
+  double Ax[N + 1], Ay[N + 1], Az[N + 1];
+  shift_poly<N>(ux, th - 1.0, Ax);
+  shift_poly<N>(uy, th - 1.0, Ay);
+  shift_poly<N>(uz, th - 1.0, Az);
+#pragma unroll
+  for (int ax = 0; ax <= N; ++ax)
+#pragma unroll
+    for (int ay = 0; ay <= N; ++ay)
+#pragma unroll
+      for (int az = 0; az <= N; ++az)
+        if (ax + ay + az <= N)
+          m[static_cast<size_t>(midx(ax, ay, az)) * stride + node] = static_cast<float>(rho * Ax[ax] * Ay[ay] * Az[az]);
+}
+
+}  // namespace lbsmrt

@@ -126,6 +126,49 @@ class Lattice:
                                          _stream_ptr()), "lbsmrt_loss_seed")
         return lam
 
+    # -- moment-state form (periodic box contexts; see lbsmrt_step_moment_state) --------
+    def moment_state_len(self):
+        """(m_len, work_len) in floats."""
+        m, w = ctypes.c_longlong(), ctypes.c_longlong()
+        C.check(C.lib().lbsmrt_moment_state_len(self._h, ctypes.byref(m), ctypes.byref(w)), "lbsmrt_moment_state_len")
+        return m.value, w.value
+
+    def new_moment_state(self):
+        return torch.empty((self.M, self.f_stride), dtype=torch.float32, device=self.device)
+
+    def new_moment_work(self):
+        return torch.empty(self.moment_state_len()[1], dtype=torch.float32, device=self.device)
+
+    def equilibrium_moments(self, fields, out=None):
+        """fields: float64 (5, n_nodes) rows rho, u_x, u_y, u_z, theta -> moment state (M, f_stride)."""
+        m = self.new_moment_state() if out is None else out
+        C.check(C.lib().lbsmrt_equilibrium_moments(self._h, _dev_ptr(fields, torch.float64, "fields"),
+                                                   _dev_ptr(m, torch.float32, "m"), _stream_ptr()),
+                "lbsmrt_equilibrium_moments")
+        return m
+
+    def project_state(self, f, out=None):
+        """Own-node moments m_alpha = sum_i f_i He_alpha(c_i) of a population state."""
+        m = self.new_moment_state() if out is None else out
+        C.check(C.lib().lbsmrt_project_state(self._h, _dev_ptr(f, torch.float32, "f"), _dev_ptr(m, torch.float32, "m"),
+                                             _stream_ptr()), "lbsmrt_project_state")
+        return m
+
+    def expand_state(self, m, out=None):
+        """Population state f_i = w_i sum_alpha m_alpha He_alpha(c_i) / alpha! of a moment state."""
+        f = self.new_state() if out is None else out
+        C.check(C.lib().lbsmrt_expand_state(self._h, _dev_ptr(m, torch.float32, "m"), _dev_ptr(f, torch.float32, "f"),
+                                            _stream_ptr()), "lbsmrt_expand_state")
+        return f
+
+    def step_moment_state(self, m_a, m_b, work, n_steps=1):
+        """Advance a moment state n_steps; returns whichever of m_a, m_b holds the result."""
+        C.check(C.lib().lbsmrt_step_moment_state(self._h, _dev_ptr(m_a, torch.float32, "m_a"),
+                                                 _dev_ptr(m_b, torch.float32, "m_b"),
+                                                 _dev_ptr(work, torch.float32, "work"), int(n_steps), _stream_ptr()),
+                "lbsmrt_step_moment_state")
+        return m_a if n_steps % 2 == 0 else m_b
+
     def set_tau(self, tau):
         """Replace the relaxation times ({(n, m): tau_nm}); missing entries keep their value."""
         self.tau.update({k: float(v) for k, v in tau.items()})

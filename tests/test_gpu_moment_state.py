@@ -1,0 +1,203 @@
+"""Moment-state form of the periodic step (lbsmrt_step_moment_state) through the C ABI.
+
+The regularised rebuild makes a post-collision state a function of its M moments, so the
+moment-state step must agree with the population step on the expanded state (both FP32
+state, different rounding points), and with the FP64 oracle.  Boxes with ragged sizes (not
+multiples of the 256-wide rows or of the line chunks of the z and y passes), all four compiled
+(stencil, N) pairs and a non-zero frame shift; one step at 256^3 over every node."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2401_11086_amd import workloads as W
+
+from cases import D1Q7, D1Q9, box_case
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-5
+TOL_PROFILE = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _fields(shape, shift, r, seed):
+    """Seeded random perturbation of a Maxwellian around u = r k (lab frame)."""
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    f = np.empty((5, n))
+    f[0] = 1.0 + 0.03 * rng.uniform(-1, 1, n)
+    for k in range(3):
+        f[1 + k] = r * shift[k] + 0.05 * rng.uniform(-1, 1, n)
+    f[4] = 1.0 + 0.03 * rng.uniform(-1, 1, n)
+    return f
+
+
+def _lattice(stencil, N, shape, shift=(0, 0, 0), precision="fp64_contract", n_ref=32):
+    from paper_2401_11086_amd import Lattice
+    ab, deg = stencil
+    vs = O.make_velocity_set(ab, deg)
+    tau20 = 0.05 * n_ref * vs.r
+    tau = {key: float(v) * tau20 for key, v in O.TAU_STAR_SMRT.items() if key[0] <= N}
+    nx, ny, nz = shape
+    lat = Lattice(ab, deg, N, tau, [dict(nx=nx, ny=ny, nz=nz, bc_x=0)], shift_k=shift, precision=precision)
+    return lat, vs, tau
+
+
+def _noisy_moments(torch, lat, fields, seed, amp=0.02):
+    """Equilibrium moments with multiplicative noise on every moment of order >= 2."""
+    m = lat.equilibrium_moments(torch.tensor(fields, dtype=torch.float64, device="cuda"))
+    n = lat.n_nodes
+    noise = torch.tensor(W.state_noise((lat.M - 4, n), seed=seed, amp=amp), dtype=torch.float32, device="cuda")
+    m[4:, :n] *= noise
+    return m
+
+
+CASES = [
+    ("q343_n4_20x12x30", D1Q7, 4, (20, 12, 30), (0, 0, 0)),
+    ("q343_n3_9x8x7", D1Q7, 3, (9, 8, 7), (0, 0, 0)),
+    ("q343_n4_shift_16x11x13", D1Q7, 4, (16, 11, 13), (1, 0, -1)),
+    ("q729_n4_13x11x12", D1Q9, 4, (13, 11, 12), (0, 0, 0)),
+    ("q729_n5_12x10x46", D1Q9, 5, (12, 10, 46), (0, 0, 0)),
+    ("q343_n4_300x3x2", D1Q7, 4, (300, 3, 2), (0, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("name,stencil,N,shape,shift", CASES, ids=[c[0] for c in CASES])
+def test_moment_state_matches_population_step(torch, name, stencil, N, shape, shift):
+    lat, vs, _ = _lattice(stencil, N, shape, shift)
+    n = lat.n_nodes
+    m0 = _noisy_moments(torch, lat, _fields(shape, shift, vs.r, seed=3), seed=4)
+    f0 = lat.expand_state(m0)
+    fb = lat.new_state()
+    steps = 3
+    f_pop = lat.step(f0.clone(), fb, steps)
+    mb, work = lat.new_moment_state(), lat.new_moment_work()
+    m_out = lat.step_moment_state(m0, mb, work, steps)
+    lat.sync()
+    f_mom = lat.expand_state(m_out)
+    torch.cuda.synchronize()
+    a = f_mom[:, :n].double()
+    b = f_pop[:, :n].double()
+    err = float((a - b).abs().max() / b.abs().max())
+    print(f"{name}: {steps} steps, moment state vs population state {err:.2e}")
+    assert err < TOL_STEP, err
+
+
+@pytest.mark.parametrize("stencil,N", [(D1Q7, 4), (D1Q9, 5)], ids=["q343_n4", "q729_n5"])
+def test_moment_state_one_step_matches_oracle(torch, stencil, N):
+    case = box_case(8, stencil, N, n_ref=32)
+    lat, vs, _ = _lattice(stencil, N, (8, 8, 8))
+    n = lat.n_nodes
+    fields = W.fourier_box(8, seed=0)
+    m0 = _noisy_moments(torch, lat, fields, seed=5)
+    f0 = lat.expand_state(m0)
+    mb, work = lat.new_moment_state(), lat.new_moment_work()
+    m1 = lat.step_moment_state(m0, mb, work, 1)
+    lat.sync()
+    g = lat.expand_state(m1)[:, :n].double().cpu().numpy()
+    fo0 = f0[:, :n].double().cpu().numpy().reshape(-1, 8, 8, 8)
+    fo1 = O.step(fo0, case["model"], case["dom"]).reshape(g.shape)
+    err = float(np.abs(g - fo1).max() / np.abs(fo1).max())
+    print(f"one moment-state step vs FP64 oracle: {err:.2e}")
+    assert err < TOL_STEP, err
+
+
+def test_project_expand_round_trip(torch):
+    lat, vs, _ = _lattice(D1Q7, 4, (10, 9, 8))
+    n = lat.n_nodes
+    m = _noisy_moments(torch, lat, _fields((10, 9, 8), (0, 0, 0), vs.r, seed=6), seed=7)
+    f = lat.expand_state(m)
+    m2 = lat.project_state(f)
+    torch.cuda.synchronize()
+    err = float((m2[:, :n] - m[:, :n]).abs().max() / m[:, :n].abs().max())
+    assert err < 1e-6, err
+    # the equilibrium moments are the projection of the population equilibrium
+    fields = torch.tensor(_fields((10, 9, 8), (0, 0, 0), vs.r, seed=8), dtype=torch.float64, device="cuda")
+    me = lat.equilibrium_moments(fields)
+    mp = lat.project_state(lat.equilibrium(fields))
+    torch.cuda.synchronize()
+    err = float((me[:, :n] - mp[:, :n]).abs().max() / me[:, :n].abs().max())
+    assert err < 1e-6, err
+
+
+def test_box32_200_steps_moment_state_tracks_population_state(torch):
+    """Fourier box of the 256^3 workload's recipe at 32^3, 200 steps: the two state forms stay
+    within 1e-4 of each other on every moment (both FP32 states)."""
+    from paper_2401_11086_amd import _lib as C
+    lat, _, _ = _lattice(D1Q7, 4, (32, 32, 32), n_ref=32)
+    n = lat.n_nodes
+    fields = torch.tensor(W.fourier_box(32, seed=0), dtype=torch.float64, device="cuda")
+    fa = lat.equilibrium(fields)
+    ma = lat.project_state(fa)
+    fb, mb, work = lat.new_state(), lat.new_moment_state(), lat.new_moment_work()
+    f = lat.step(fa, fb, 200)
+    m = lat.step_moment_state(ma, mb, work, 200)
+    lat.sync()
+    fm = lat.expand_state(m)
+    a = lat.moments(f, C.MOM_ALAB)[:, :n]
+    b = lat.moments(fm, C.MOM_ALAB)[:, :n]
+    err = float((a - b).abs().max() / a.abs().max())
+    print(f"200 steps: moment-state vs population-state lattice moments {err:.2e}")
+    assert err < TOL_PROFILE, err
+
+
+def test_moment_state_rejects_unsupported_contexts(torch):
+    from paper_2401_11086_amd import Lattice
+    from paper_2401_11086_amd import _lib as C
+    from paper_2401_11086_amd.shocks import shock_domain
+    c_l, _ = C.solve_quadrature([1, 2, 3], 9)
+    dom, _, _ = shock_domain(1.2, 40, c_l)
+    tau = {(2, 0): 1.0, (3, 0): 1.0, (3, 1): 1.0, (4, 0): 1.0, (4, 1): 1.0, (4, 2): 1.0}
+    shock = Lattice([1, 2, 3], 9, 4, tau, [dom], shift_k=(1, 0, 0))
+    m, mb, w = shock.new_moment_state(), shock.new_moment_state(), shock.new_moment_work()
+    with pytest.raises(C.LbsmrtError) as e:
+        shock.step_moment_state(m, mb, w, 1)
+    assert e.value.status == C.E_UNSUPPORTED
+    two = Lattice([1, 2, 3], 9, 4, tau, [dict(nx=8, ny=8, nz=8), dict(nx=4, ny=4, nz=4)])
+    m, mb, w = two.new_moment_state(), two.new_moment_state(), two.new_moment_work()
+    with pytest.raises(C.LbsmrtError) as e:
+        two.step_moment_state(m, mb, w, 1)
+    assert e.value.status == C.E_UNSUPPORTED
+    box = Lattice([1, 2, 3], 9, 4, tau, [dict(nx=8, ny=8, nz=8)])
+    m, w = box.new_moment_state(), box.new_moment_work()
+    with pytest.raises(C.LbsmrtError) as e:
+        box.step_moment_state(m, m, w, 1)            # m_a == m_b
+    assert e.value.status == C.E_ARG
+    with pytest.raises(C.LbsmrtError) as e:
+        box.step_moment_state(m, w[: box.moment_state_len()[0]].view(box.M, -1), w, 1)   # m_b inside work
+    assert e.value.status == C.E_ARG
+
+
+def test_full_size_box_one_step_matches_population_step(torch):
+    """256^3 D3Q343 box (the throughput workload), one step from the same state, every node."""
+    lat, _, _ = _lattice(D1Q7, 4, (256, 256, 256), n_ref=256)
+    n = lat.n_nodes
+    fields = W.fourier_box_torch(256, "cuda", seed=0)
+    ma = lat.equilibrium_moments(fields)
+    del fields
+    fa = lat.expand_state(ma)
+    fb = lat.new_state()
+    lat.step(fa, fb, 1)
+    mb, work = lat.new_moment_state(), lat.new_moment_work()
+    lat.step_moment_state(ma, mb, work, 1)
+    lat.sync()
+    del work
+    lat.expand_state(mb, out=fa)
+    torch.cuda.synchronize()
+    worst, scale = 0.0, 0.0
+    for q0 in range(0, lat.Q, 49):
+        a = fa[q0:q0 + 49, :n]
+        b = fb[q0:q0 + 49, :n]
+        worst = max(worst, float((a - b).abs().max()))
+        scale = max(scale, float(b.abs().max()))
+    err = worst / scale
+    print(f"256^3 one step: moment state vs population state {err:.2e}")
+    assert err < TOL_STEP, err
