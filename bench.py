@@ -253,6 +253,49 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     return out
 
 
+def moment_state_bytes(lat):
+    """Algorithmic HBM bytes per node of the three moment-state passes: z reads the M moment
+    fields and writes the P2 (N+1) intermediate fields, y reads and writes P2 (N+1), x reads
+    P2 (N+1) and writes M (FP32 each)."""
+    n1 = (lat.N + 1) * (lat.N + 1) * (lat.N + 2) // 2
+    return {"pass_z": 4.0 * (lat.M + n1), "pass_y": 8.0 * n1, "pass_x_collide": 4.0 * (n1 + lat.M)}
+
+
+def time_moment_state(torch, lat, f_cur, f_other, steps, ms_pop):
+    """The same step with the state held as the M moments (lbsmrt_step_moment_state): timed from
+    the moments of the current population state, then one step of each form from that state,
+    compared over every node.  Overwrites both population buffers with valid states."""
+    ma = lat.project_state(f_cur)
+    mb, work = lat.new_moment_state(), lat.new_moment_work()
+    lat.step_moment_state(ma, mb, work, 2)
+    lat.sync()
+    ms = _time_steps(torch, lambda: lat.step_moment_state(ma, mb, work, 2), max(2, steps // 2)) / 2
+    lat.sync()
+    lat.project_state(f_cur, out=ma)
+    lat.step(f_cur, f_other, 1)
+    lat.step_moment_state(ma, mb, work, 1)
+    lat.sync()
+    lat.expand_state(mb, out=f_cur)
+    worst = scale = 0.0
+    for q0 in range(0, lat.Q, 49):
+        worst = max(worst, float((f_cur[q0:q0 + 49] - f_other[q0:q0 + 49]).abs().max()))
+        scale = max(scale, float(f_other[q0:q0 + 49].abs().max()))
+    del ma, mb, work
+    per = moment_state_bytes(lat)
+    step_bytes = sum(per.values()) * lat.n_nodes
+    out = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2),
+           "speedup_vs_population_step": round(ms_pop / ms, 3),
+           "bytes_per_node_step": {k: v for k, v in per.items()},
+           "achieved_GBs_whole_step": round(step_bytes / (ms / 1e3) / 1e9, 1),
+           "one_step_max_rel_diff_vs_population_step": worst / scale,
+           "kernels": [f"k_ms_pass_z<{lat.Q1},{lat.N},{8 * (2 * (3 if lat.Q1 == 7 else 5) + 1)}>",
+                       f"k_ms_pass_y<{lat.Q1},{lat.N},{8 * (2 * (3 if lat.Q1 == 7 else 5) + 1)}>",
+                       f"k_ms_pass_x_collide<{lat.Q1},{lat.N}>"]}
+    _progress(f"moment-state step: {ms:.3f} ms ({out['mlups']} MLUPS, {ms_pop / ms:.2f}x the population step), "
+              f"one-step difference {worst / scale:.2e}")
+    return out
+
+
 def time_shock_adjoint(torch, steps=300):
     """The adjoint-calibration shock (Ma 3, Nx 600, D3Q729, N = 5, FP64 contractions): forward and
     adjoint step times on one small domain, where each wave's latency, not HBM, sets the time."""
@@ -410,7 +453,8 @@ def main():
     assert torch.isfinite(rho).all() and abs(float(rho.mean()) - 1.0) < 1e-3
     variants = {}
     if not args.no_variants:
-        variants = time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step)
+        variants["moment_state"] = time_moment_state(torch, lat, cur, fb if cur is fa else fa, args.steps, ms_step)
+        variants.update(time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step))
         variants["shock_adjoint"] = time_shock_adjoint(torch)
         variants["batched_mach_sweep"] = time_batched(torch, steps=args.batched_steps)
 

@@ -58,7 +58,6 @@ struct lbsmrt_ctx {
   // moment-state form: one periodic domain and a stencil with compile-time taps
   bool ms_ok = false;
   MomentTaps32 ms_k32{};
-  MomentTaps64 ms_k64{};
 };
 
 namespace {
@@ -178,7 +177,7 @@ struct Launch {
                          c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
   }
   // moment-state form: line chunk of the z and y passes (a multiple of the tap window)
-  static constexpr int kMsChunk = 4 * (2 * Taps1D<Q1>::H + 1);
+  static constexpr int kMsChunk = 8 * (2 * Taps1D<Q1>::H + 1);
   static void ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, float* dst, float* t1, float* t2,
                       hipStream_t s) {
     const unsigned gx = static_cast<unsigned>((G.nx + 255) / 256);
@@ -186,7 +185,7 @@ struct Launch {
                        s, c->ms_k32, G, src, t1);
     hipLaunchKernelGGL((k_ms_pass_y<Q1, N, kMsChunk>), dim3(gx, G.nz, (G.ny + kMsChunk - 1) / kMsChunk), dim3(256), 0,
                        s, c->ms_k32, G, t1, t2);
-    hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3(gx, G.ny, G.nz), dim3(256), 0, s, c->L, c->ms_k64, G, t2,
+    hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3(gx, G.ny, G.nz), dim3(256), 0, s, c->L, c->ms_k32, G, t2,
                        dst);
   }
   static bool ms_taps_match(const lbsmrt_ctx* c) {
@@ -447,9 +446,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   for (int t = 0; t <= p; ++t)
     for (int b = 0; b <= c->N; ++b)
       for (int a = 0; a <= c->N; ++a) {
-        const double k = L.He64[p + t][b] * L.Rw64[p + t][a];
-        c->ms_k64.K[t][b][a] = k;
-        c->ms_k32.K[t][b][a] = static_cast<float>(k);
+        c->ms_k32.K[t][b][a] = static_cast<float>(L.He64[p + t][b] * L.Rw64[p + t][a]);
       }
 
   hipStream_t s = static_cast<hipStream_t>(stream);

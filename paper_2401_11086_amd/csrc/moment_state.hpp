@@ -16,7 +16,7 @@
 // Passes z and y march each work-item along its line with a register ring of the last W rows
 // (W = 2 max|e| + 1), so every input row is read once per line chunk of T rows; the taps are
 // folded over +-e (K(-e) = (-1)^(a+b) K(e)).  Pass x reads its row's shifted neighbours directly
-// (same cache lines as the row itself) and accumulates in FP64 for the collision.
+// (same cache lines as the row itself); the collision runs in FP64.
 #pragma once
 #include "kernels.hpp"
 
@@ -42,9 +42,6 @@ struct Taps1D<9> {
 // K[t][b][a] = He_b(c) w He_a(c) / a! at the non-negative tap t (c = r e_t).
 struct MomentTaps32 {
   float K[kMaxQ1 / 2 + 1][kMaxN + 1][kMaxN + 1];
-};
-struct MomentTaps64 {
-  double K[kMaxQ1 / 2 + 1][kMaxN + 1][kMaxN + 1];
 };
 
 struct MsGeom {
@@ -172,14 +169,69 @@ __global__ __launch_bounds__(256) void k_ms_pass_y(MomentTaps32 K, MsGeom G, con
     }
 }
 
-// Pass x + collision: t2[ax P2 + pair(by, bz)] -> a[bx, by, bz] (FP64), SMRT collision, store a'.
+// One (by, bz) group of pass x: a[bx, by, bz] = sum_ax sum_e K_{bx ax}(e) t2[ax, by, bz](x - e - k_x)
+// for bx <= N - by - bz (FP32 sums, taps folded over +-e).
+template <int Q1, int N, int BY, int BZ>
+__device__ __forceinline__ void x_group(const MomentTaps32& K, const float* __restrict__ t2, long long stride,
+                                        const unsigned (&op)[Taps1D<Q1>::p + 1],
+                                        const unsigned (&om)[Taps1D<Q1>::p + 1], float (&a32)[n_moments(N)]) {
+  using S = Taps1D<Q1>;
+  constexpr int P2 = n_sym(N);
+  constexpr int NO = N - BY - BZ;
+  float acc[NO + 1];
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.f;
+#pragma unroll
+  for (int a = 0; a <= N; ++a) {
+    const float* __restrict__ src = t2 + static_cast<size_t>(a * P2 + pair_pos(BY, BZ)) * stride;
+    if (!(a & 1)) {
+      const float c = load_at(src, op[0]);
+#pragma unroll
+      for (int b = 0; b <= NO; b += 2) acc[b] = fmaf(K.K[0][b][a], c, acc[b]);
+    }
+#pragma unroll
+    for (int t = 1; t <= S::p; ++t) {
+      const float vp = load_at(src, op[t]);
+      const float vm = load_at(src, om[t]);
+      const float s = vp + vm, dd = vp - vm;
+#pragma unroll
+      for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
+    }
+  }
+  // Finish each group before the next one's loads: the empty asm statements pin the sums here
+  // and order the loads, otherwise every loaded value stays live until the collision.
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) {
+    asm volatile("" : "+v"(acc[b]));
+    a32[midx(b, BY, BZ)] = acc[b];
+  }
+  asm volatile("" ::: "memory");
+}
+
+// All groups (by, bz), by + bz <= N, in compile-time order.
+template <int Q1, int N, int BY, int BZ>
+__device__ __forceinline__ void x_groups(const MomentTaps32& K, const float* __restrict__ t2, long long stride,
+                                         const unsigned (&op)[Taps1D<Q1>::p + 1],
+                                         const unsigned (&om)[Taps1D<Q1>::p + 1], float (&a32)[n_moments(N)]) {
+  if constexpr (BY <= N) {
+    if constexpr (BY + BZ <= N) {
+      x_group<Q1, N, BY, BZ>(K, t2, stride, op, om, a32);
+      x_groups<Q1, N, BY, BZ + 1>(K, t2, stride, op, om, a32);
+    } else {
+      x_groups<Q1, N, BY + 1, 0>(K, t2, stride, op, om, a32);
+    }
+  }
+}
+
+// Pass x + collision: t2[ax P2 + pair(by, bz)] -> a[bx, by, bz], SMRT collision (FP64), store a'.
+// The x-stage sums run in FP32 like the other two passes (the loads are FP32, and FP32 and FP64
+// FMAs issue at the same rate here, so converting every tap would only add work).
 // Grid (ceil(nx/256), ny, nz).
 template <int Q1, int N>
-__global__ __launch_bounds__(256) void k_ms_pass_x_collide(LatticeConst L, MomentTaps64 K, MsGeom G,
+__global__ __launch_bounds__(256) void k_ms_pass_x_collide(LatticeConst L, MomentTaps32 K, MsGeom G,
                                                            const float* __restrict__ t2, float* __restrict__ m_out) {
   using S = Taps1D<Q1>;
   constexpr int M = n_moments(N);
-  constexpr int P2 = n_sym(N);
   const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
   if (x >= G.nx) return;
   const int y = static_cast<int>(blockIdx.y);
@@ -196,42 +248,11 @@ __global__ __launch_bounds__(256) void k_ms_pass_x_collide(LatticeConst L, Momen
     op[t] = static_cast<unsigned>(row + sp) * 4u;
     om[t] = static_cast<unsigned>(row + sm) * 4u;
   }
+  float a32[M];
+  x_groups<Q1, N, 0, 0>(K, t2, G.stride, op, om, a32);
   double d[M];
 #pragma unroll
-  for (int by = 0; by <= N; ++by)
-#pragma unroll
-    for (int bz = 0; bz <= N; ++bz) {
-      if (by + bz > N) continue;
-      double acc[N + 1];
-#pragma unroll
-      for (int b = 0; b <= N; ++b) acc[b] = 0.0;
-#pragma unroll
-      for (int a = 0; a <= N; ++a) {
-        const float* __restrict__ src = t2 + static_cast<size_t>(a * P2 + pair_pos(by, bz)) * G.stride;
-        if (!(a & 1)) {
-          const double c = static_cast<double>(load_at(src, op[0]));
-#pragma unroll
-          for (int b = 0; b <= N; b += 2) acc[b] = fma(K.K[0][b][a], c, acc[b]);
-        }
-#pragma unroll
-        for (int t = 1; t <= S::p; ++t) {
-          const double vp = static_cast<double>(load_at(src, op[t]));
-          const double vm = static_cast<double>(load_at(src, om[t]));
-          const double s = vp + vm, dd = vp - vm;
-#pragma unroll
-          for (int b = 0; b <= N; ++b) acc[b] = fma(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
-        }
-      }
-      // Finish each group before the next one's loads: the empty asm statements pin the sums
-      // here and order the loads, otherwise every loaded value stays live until the collision.
-#pragma unroll
-      for (int bx = 0; bx <= N; ++bx)
-        if (bx + by + bz <= N) {
-          asm volatile("" : "+v"(acc[bx]));
-          d[midx(bx, by, bz)] = acc[bx];
-        }
-      asm volatile("" ::: "memory");
-    }
+  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
   double S5[5];
   sums_from_a<N>(d, L, S5);
   Macro mac = macro_from_sums(L, S5, G.err);
