@@ -72,9 +72,9 @@ def recorded_traffic(workload, precision):
 def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
     """The FP64 oracle on a sample_edge^3 box of the same Fourier workload (same modes and
     relaxation times), `steps` steps from the library's FP32 equilibrium state; MLUPS scaled
-    from that sample.  The same steps on the GPU in each contraction precision give each form's
-    error against the oracle (max |f_gpu - f_oracle| / max |f_oracle|, and the largest deviation
-    of rho and theta)."""
+    from that sample.  The same steps on the GPU in each contraction precision, and in the
+    moment-state form, give each form's error against the oracle (max |f_gpu - f_oracle| /
+    max |f_oracle|, and the largest deviation of rho and theta)."""
     import numpy as np
 
     import oracle as O
@@ -104,6 +104,14 @@ def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
         cur = lat.step(fa, fb, steps)
         lat.sync()
         gpu[precision] = cur[:, :n].double().cpu().numpy()
+        if precision == "fp64_contract":
+            # the moment-state form from the same state (its moments are the projection of it)
+            ma = lat.project_state(lat.equilibrium(fields))
+            mb, work = lat.new_moment_state(), lat.new_moment_work()
+            m = lat.step_moment_state(ma, mb, work, steps)
+            lat.sync()
+            gpu["moment_state"] = lat.expand_state(m)[:, :n].double().cpu().numpy()
+            del ma, mb, work, m
         lat.close()
     f = f32.astype(np.float64).reshape(vs.Q, sample_edge, sample_edge, sample_edge)
     t0 = time.perf_counter()
