@@ -296,8 +296,7 @@ def time_moment_state(torch, lat, f_cur, f_other, steps, ms_pop):
            "bytes_per_node_step": {k: v for k, v in per.items()},
            "achieved_GBs_whole_step": round(step_bytes / (ms / 1e3) / 1e9, 1),
            "one_step_max_rel_diff_vs_population_step": worst / scale,
-           "kernels": [f"k_ms_pass_z<{lat.Q1},{lat.N},{8 * (2 * (3 if lat.Q1 == 7 else 5) + 1)}>",
-                       f"k_ms_pass_y<{lat.Q1},{lat.N},{8 * (2 * (3 if lat.Q1 == 7 else 5) + 1)}>",
+           "kernels": [f"k_ms_pass_z<{lat.Q1},{lat.N}>", f"k_ms_pass_y<{lat.Q1},{lat.N}>",
                        f"k_ms_pass_x_collide<{lat.Q1},{lat.N}>"]}
     _progress(f"moment-state step: {ms:.3f} ms ({out['mlups']} MLUPS, {ms_pop / ms:.2f}x the population step), "
               f"one-step difference {worst / scale:.2e}")

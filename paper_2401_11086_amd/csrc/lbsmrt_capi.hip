@@ -176,17 +176,27 @@ struct Launch {
       hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
                          c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
   }
-  // moment-state form: line chunk of the z and y passes (a multiple of the tap window)
-  static constexpr int kMsChunk = 8 * (2 * Taps1D<Q1>::H + 1);
+  // Moment-state form.  Line chunk of the z and y passes: a multiple of the tap window W, as long
+  // as possible (the W - 1 halo rows are read again per chunk) while the launch still has about
+  // kMsLanes work-items (4 waves per SIMD of the chip), and at most 8 W.
+  static constexpr int kMsWindow = 2 * Taps1D<Q1>::H + 1;
+  static constexpr long long kMsLanes = 262144;
+  static int ms_chunk(long long lines, int len) {
+    const long long chunks = std::max(1LL, (kMsLanes + lines - 1) / lines);
+    const long long rows = (len + chunks - 1) / chunks;
+    const long long r = std::min(8LL, std::max(1LL, rows / kMsWindow));
+    return static_cast<int>(r) * kMsWindow;
+  }
   static void ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, float* dst, float* t1, float* t2,
                       hipStream_t s) {
-    const unsigned gx = static_cast<unsigned>((G.nx + 255) / 256);
-    hipLaunchKernelGGL((k_ms_pass_z<Q1, N, kMsChunk>), dim3(gx, G.ny, (G.nz + kMsChunk - 1) / kMsChunk), dim3(256), 0,
-                       s, c->ms_k32, G, src, t1);
-    hipLaunchKernelGGL((k_ms_pass_y<Q1, N, kMsChunk>), dim3(gx, G.nz, (G.ny + kMsChunk - 1) / kMsChunk), dim3(256), 0,
-                       s, c->ms_k32, G, t1, t2);
-    hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3(gx, G.ny, G.nz), dim3(256), 0, s, c->L, c->ms_k32, G, t2,
-                       dst);
+    const long long lz = static_cast<long long>(G.nx) * G.ny, ly = static_cast<long long>(G.nx) * G.nz;
+    const int Tz = ms_chunk(lz, G.nz), Ty = ms_chunk(ly, G.ny);
+    hipLaunchKernelGGL((k_ms_pass_z<Q1, N>), dim3(static_cast<unsigned>((lz + 255) / 256), (G.nz + Tz - 1) / Tz),
+                       dim3(256), 0, s, c->ms_k32, G, src, t1, Tz);
+    hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
+                       dim3(256), 0, s, c->ms_k32, G, t1, t2, Ty);
+    hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
+                       c->ms_k32, G, t2, dst);
   }
   static bool ms_taps_match(const lbsmrt_ctx* c) {
     const int p = Q1 / 2;

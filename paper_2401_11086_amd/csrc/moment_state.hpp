@@ -14,7 +14,8 @@
 // float32 [P2 (N+1)][stride] each.  Every node of one periodic domain (x fastest).
 //
 // Passes z and y march each work-item along its line with a register ring of the last W rows
-// (W = 2 max|e| + 1), so every input row is read once per line chunk of T rows; the taps are
+// (W = 2 max|e| + 1), so every input row is read once per line chunk of T rows (T a multiple of
+// W, chosen by the host so that the launch has enough waves); the taps are
 // folded over +-e (K(-e) = (-1)^(a+b) K(e)).  Pass x reads its row's shifted neighbours directly
 // (same cache lines as the row itself); the collision runs in FP64.
 #pragma once
@@ -55,15 +56,14 @@ struct MsGeom {
 // March of one line: outputs at positions p0 .. p0 + T - 1 (< len) of the line whose position q
 // has byte offset base + q * step.  Inputs: fields fin[a], a < nf (the 1D index a of the
 // convolved axis); outputs: fields fout[b], b < no (1D index b).
-template <int Q1, int N, int T>
+template <int Q1, int N>
 __device__ __forceinline__ void march_line(const MomentTaps32& K, const float* __restrict__ in,
                                            float* __restrict__ out, long long stride, const int (&fin)[N + 1],
                                            int nf, const int (&fout)[N + 1], int no, unsigned base, unsigned step,
-                                           int len, int p0, int kshift) {
+                                           int len, int p0, int T, int kshift) {
   using S = Taps1D<Q1>;
   constexpr int H = S::H;
-  constexpr int W = 2 * H + 1;
-  static_assert(T % W == 0, "chunk length must be a multiple of the window");
+  constexpr int W = 2 * H + 1;   // T is a multiple of W (checked by the host)
   const float* __restrict__ src[N + 1];
 #pragma unroll
   for (int a = 0; a <= N; ++a) src[a] = in + static_cast<size_t>(a < nf ? fin[a] : fin[0]) * stride;
@@ -122,15 +122,16 @@ __device__ __forceinline__ void march_line(const MomentTaps32& K, const float* _
   }
 }
 
-// Pass z: a'[ax, ay, az] -> t1[pair(ax, ay) (N+1) + bz].  Grid (ceil(nx/256), ny, ceil(nz/T)).
-template <int Q1, int N, int T>
+// Pass z: a'[ax, ay, az] -> t1[pair(ax, ay) (N+1) + bz].  One work-item per z line (x, y), the
+// lines numbered x fastest over the plane (so a wave reads contiguous 256 B); grid
+// (ceil(nx ny / 256), ceil(nz / T)), each work-item marching T rows.
+template <int Q1, int N>
 __global__ __launch_bounds__(256) void k_ms_pass_z(MomentTaps32 K, MsGeom G, const float* __restrict__ m,
-                                                   float* __restrict__ t1) {
-  const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
-  if (x >= G.nx) return;
-  const int y = static_cast<int>(blockIdx.y);
-  const int z0 = static_cast<int>(blockIdx.z) * T;
-  const unsigned base = static_cast<unsigned>(x + G.nx * y) * 4u;
+                                                   float* __restrict__ t1, int T) {
+  const int line = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (line >= G.nx * G.ny) return;
+  const int z0 = static_cast<int>(blockIdx.y) * T;
+  const unsigned base = static_cast<unsigned>(line) * 4u;
   const unsigned step = static_cast<unsigned>(G.nx * G.ny) * 4u;
 #pragma unroll 1
   for (int ax = 0; ax <= N; ++ax)
@@ -141,19 +142,21 @@ __global__ __launch_bounds__(256) void k_ms_pass_z(MomentTaps32 K, MsGeom G, con
       for (int a = 0; a <= N; ++a) fin[a] = midx(ax, ay, a <= N - ax - ay ? a : 0);
 #pragma unroll
       for (int b = 0; b <= N; ++b) fout[b] = pair_pos(ax, ay) * (N + 1) + b;
-      march_line<Q1, N, T>(K, m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, G.k[2]);
+      march_line<Q1, N>(K, m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, T, G.k[2]);
     }
 }
 
-// Pass y: t1[pair(ax, ay) (N+1) + bz] -> t2[ax P2 + pair(by, bz)].  Grid (ceil(nx/256), nz, ceil(ny/T)).
-template <int Q1, int N, int T>
+// Pass y: t1[pair(ax, ay) (N+1) + bz] -> t2[ax P2 + pair(by, bz)].  One work-item per y line
+// (x, z), x fastest; grid (ceil(nx nz / 256), ceil(ny / T)).
+template <int Q1, int N>
 __global__ __launch_bounds__(256) void k_ms_pass_y(MomentTaps32 K, MsGeom G, const float* __restrict__ t1,
-                                                   float* __restrict__ t2) {
+                                                   float* __restrict__ t2, int T) {
   constexpr int P2 = n_sym(N);
-  const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
-  if (x >= G.nx) return;
-  const int z = static_cast<int>(blockIdx.y);
-  const int y0 = static_cast<int>(blockIdx.z) * T;
+  const int line = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (line >= G.nx * G.nz) return;
+  const int x = line % G.nx;
+  const int z = line / G.nx;
+  const int y0 = static_cast<int>(blockIdx.y) * T;
   const unsigned base = static_cast<unsigned>(x + G.nx * G.ny * z) * 4u;
   const unsigned step = static_cast<unsigned>(G.nx) * 4u;
 #pragma unroll 1
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(256) void k_ms_pass_y(MomentTaps32 K, MsGeom G, con
       for (int a = 0; a <= N; ++a) fin[a] = pair_pos(ax, a <= N - ax ? a : 0) * (N + 1) + bz;
 #pragma unroll
       for (int b = 0; b <= N; ++b) fout[b] = ax * P2 + pair_pos(b <= N - bz ? b : 0, bz);
-      march_line<Q1, N, T>(K, t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, G.k[1]);
+      march_line<Q1, N>(K, t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, T, G.k[1]);
     }
 }
 
@@ -228,7 +231,7 @@ __device__ __forceinline__ void x_groups(const MomentTaps32& K, const float* __r
 // FMAs issue at the same rate here, so converting every tap would only add work).
 // Grid (ceil(nx/256), ny, nz).
 template <int Q1, int N>
-__global__ __launch_bounds__(256) void k_ms_pass_x_collide(LatticeConst L, MomentTaps32 K, MsGeom G,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_pass_x_collide(LatticeConst L, MomentTaps32 K, MsGeom G,
                                                            const float* __restrict__ t2, float* __restrict__ m_out) {
   using S = Taps1D<Q1>;
   constexpr int M = n_moments(N);
