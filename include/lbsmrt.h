@@ -50,7 +50,8 @@ typedef enum {
   LBSMRT_E_HIP = 4,          /* a HIP runtime call failed */
   LBSMRT_E_NOMEM = 5,        /* device or host allocation failed */
   LBSMRT_E_UNSUPPORTED = 6   /* valid but not built: a (Q1, N) pair with no compiled kernel, the
-                                reserved precision, regularized = 0, or a launch setting the
+                                reserved precision, regularized = 0 with FP32 contractions (or with
+                                the adjoint, the persistent launch or the moment state), or a launch setting the
                                 context does not allow */
 } lbsmrt_status;
 
@@ -73,7 +74,10 @@ typedef struct {
   double rho_ref;              /* density at which tau[][] holds */
   int    tau_density_scaling;  /* 1: tau_nm(x) = tau_nm * rho_ref / rho(x) (viscosity ~ theta) */
   int    tau_offset_half;      /* 1: tau_bar = tau + 1/2 (trapezoidal discretisation); 0: tau_bar = tau */
-  int    regularized;          /* 1 (only value supported): f rebuilt from its M moments each step */
+  int    regularized;          /* 1: f* rebuilt from the M relaxed moments, f* = R a' (eq:fi, default);
+                                  0: additive collision f* = g + R (a' - a), which keeps the part of
+                                  the pulled g outside the Hermite span (needs LBSMRT_FP64_CONTRACT;
+                                  one lane per node; reads g twice: 12 Q bytes per node-step) */
   int    precision;            /* lbsmrt_precision of the projection/reconstruction contractions */
 } lbsmrt_lattice_desc;
 
@@ -133,7 +137,8 @@ enum { LBSMRT_LAUNCH_DIRECT = 0, LBSMRT_LAUNCH_GRAPH = 1, LBSMRT_LAUNCH_PERSISTE
  * same split when lanes_per_node is 4 or 8 and one lane per node otherwise.  Synchronous.
  * E_ARG for an unknown mode, size, lanes_per_node or odd graph_steps; E_UNSUPPORTED for
  * lanes_per_node > 1 unless the context has shock domains, LBSMRT_FP64_CONTRACT and a state
- * below 4 GiB (Q * f_stride * 4 bytes), or if the persistent kernel cannot be made resident.
+ * below 4 GiB (Q * f_stride * 4 bytes) and the rebuilt collision, for the persistent mode of an
+ * additive-collision context, or if the persistent kernel cannot be made resident.
  * A new context starts in direct mode with work-groups of 256 (64 if no domain reaches 4096
  * nodes) and one lane per node; an eligible context with at most 8192 nodes starts with eight,
  * one with at most 16384 nodes with four. */
@@ -180,7 +185,7 @@ lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* ctx, const double* fields, float* f
  * to dL_dtau[n][m] (float64 [6][3] in device memory, accumulated, fixed
  * summation order so results are reproducible).  f_t, lam_next, lam_t are
  * [Q][f_stride] float32 device buffers; lam_t must not alias the others.
- * Asynchronous. */
+ * E_UNSUPPORTED for an additive-collision context (regularized = 0).  Asynchronous. */
 lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* ctx, const float* f_t, const float* lam_next,
                                   float* lam_t, double* dL_dtau, void* stream);
 

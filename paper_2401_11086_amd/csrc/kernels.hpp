@@ -482,15 +482,70 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
   if constexpr (LPN > 1) group_allreduce<LPN, Shape<Q1, N>::M>(a);
 }
 
-// One z line of the rebuild: f[iz] = sum_az Rw_az(iz) v[az], stored as FP32.
-template <int Q1, int N, bool NT = false>
+// Per-slab source of the additive collision (no addition for the regularised rebuild).
+struct NoAdd {
+  static constexpr bool active = false;
+  __device__ double operator()(int, int) const { return 0.0; }
+};
+struct NoAddSource {
+  __device__ NoAdd slab(int) const { return NoAdd{}; }
+};
+
+// Additive collision f* = g + R (a' - a): the pulled populations g of slab ix, loaded again at
+// store time with the gather's addressing (uniform slab base, ghost columns at shock ends).
+template <int Q1, bool SHOCK>
+struct PulledSlab {
+  static constexpr bool active = true;
+  const float* __restrict__ fx;
+  const float* __restrict__ ghosts;
+  const Pull<Q1>* P;
+  long long stride;
+  int n_ghost;
+  unsigned xoff, goff;
+  bool ghost, any_ghost;
+  __device__ double operator()(int iy, int iz) const {
+    float v = load_at(fx + static_cast<size_t>(iy * Q1 + iz) * stride, xoff + P->yo[iy] + P->zo[iz]);
+    if (SHOCK && any_ghost) {
+      const float gv = load_at(ghosts + static_cast<size_t>(iy * Q1 + iz) * n_ghost, goff);
+      v = ghost ? gv : v;
+    }
+    return static_cast<double>(v);
+  }
+};
+template <int Q1, bool SHOCK>
+struct PulledSource {
+  const LatticeConst* L;
+  const StepArgs* A;
+  const float* __restrict__ f;
+  const Pull<Q1>* P;
+  __device__ PulledSlab<Q1, SHOCK> slab(int ix) const {
+    PulledSlab<Q1, SHOCK> s;
+    const int xs = source_x<Q1>(*L, *P, ix);
+    s.fx = f + static_cast<size_t>(ix * Q1 * Q1) * A->stride;
+    s.ghosts = A->ghosts;
+    s.P = P;
+    s.stride = A->stride;
+    s.n_ghost = A->n_ghost;
+    s.ghost = SHOCK && xs < 0;
+    s.xoff = static_cast<unsigned>(P->row + (s.ghost ? 0 : xs)) * 4u;
+    s.any_ghost = SHOCK && __any(s.ghost);
+    s.goff = static_cast<unsigned>(ix * Q1 * Q1 * A->n_ghost + P->gcol + (xs == -2 ? 1 : 0)) * 4u;
+    return s;
+  }
+};
+
+// One z line of the rebuild: f[iz] = sum_az Rw_az(iz) v[az] (+ g[iy][iz] for the additive
+// collision), stored as FP32.
+template <int Q1, int N, bool NT = false, class SL = NoAdd>
 __device__ __forceinline__ void fold_line_store(const LatticeConst& L, const double (&v)[N + 1],
-                                                float* __restrict__ line_base, long long stride, unsigned off) {
+                                                float* __restrict__ line_base, long long stride, unsigned off,
+                                                const SL& add = SL{}, int iy = 0) {
   constexpr int p = Q1 / 2;
   {
     double s = 0.0;
 #pragma unroll
     for (int az = 0; az <= N; az += 2) s = fma(v[az], L.Rw64[p][az], s);
+    if constexpr (SL::active) s += add(iy, p);
     store_pop<NT>(line_base + static_cast<size_t>(p) * stride, off, static_cast<float>(s));
   }
 #pragma unroll
@@ -501,16 +556,22 @@ __device__ __forceinline__ void fold_line_store(const LatticeConst& L, const dou
       if (az & 1) o = fma(v[az], L.Rw64[p + j][az], o);
       else e = fma(v[az], L.Rw64[p + j][az], e);
     }
-    store_pop<NT>(line_base + static_cast<size_t>(p + j) * stride, off, static_cast<float>(e + o));
-    store_pop<NT>(line_base + static_cast<size_t>(p - j) * stride, off, static_cast<float>(e - o));
+    double hi = e + o, lo = e - o;
+    if constexpr (SL::active) {
+      hi += add(iy, p + j);
+      lo += add(iy, p - j);
+    }
+    store_pop<NT>(line_base + static_cast<size_t>(p + j) * stride, off, static_cast<float>(hi));
+    store_pop<NT>(line_base + static_cast<size_t>(p - j) * stride, off, static_cast<float>(lo));
   }
 }
 
-// Rebuild (eq:fi with 1/alpha!) in FP64, folded in y and z, and store to the own node.
-template <int Q1, int N, int LPN = 1, bool NT = false>
+// Rebuild (eq:fi with 1/alpha!) in FP64, folded in y and z, and store to the own node.  With an
+// additive source (LPN = 1 only) every stored population also gets its pulled value g added.
+template <int Q1, int N, int LPN = 1, bool NT = false, class SRC = NoAddSource>
 LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[Shape<Q1, N>::M],
                                                     float* __restrict__ out, long long stride, int node,
-                                                    int sub = 0) {
+                                                    int sub = 0, const SRC& src = SRC{}) {
   constexpr int p = Q1 / 2;
   constexpr int P2 = Shape<Q1, N>::P2;
   // With LPN > 1 every lane makes the same number of passes; a lane with no slab left rebuilds
@@ -538,6 +599,7 @@ LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[
         u2[pair_pos(ay, az)] = s;
       }
     float* __restrict__ slab = LPN == 1 ? out + static_cast<size_t>(ix * Q1 * Q1) * stride : out;
+    const auto add = src.slab(ix);
     {
       double v[N + 1];
 #pragma unroll
@@ -548,7 +610,7 @@ LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[
           if (ay + az <= N) s = fma(u2[pair_pos(ay, az)], L.Rw64[p][ay], s);
         v[az] = s;
       }
-      fold_line_store<Q1, N, NT>(L, v, slab + static_cast<size_t>(p * Q1) * stride, stride, off);
+      fold_line_store<Q1, N, NT>(L, v, slab + static_cast<size_t>(p * Q1) * stride, stride, off, add, p);
     }
 #pragma unroll
     for (int j = 1; j <= p; ++j) {
@@ -565,8 +627,8 @@ LBSMRT_PHASE void reconstruct_store64(const LatticeConst& L, const double (&ap)[
         vp[az] = e + o;
         vm[az] = e - o;
       }
-      fold_line_store<Q1, N, NT>(L, vp, slab + static_cast<size_t>((p + j) * Q1) * stride, stride, off);
-      fold_line_store<Q1, N, NT>(L, vm, slab + static_cast<size_t>((p - j) * Q1) * stride, stride, off);
+      fold_line_store<Q1, N, NT>(L, vp, slab + static_cast<size_t>((p + j) * Q1) * stride, stride, off, add, p + j);
+      fold_line_store<Q1, N, NT>(L, vm, slab + static_cast<size_t>((p - j) * Q1) * stride, stride, off, add, p - j);
     }
   }
 }
@@ -704,19 +766,27 @@ enum : int { kPrecFp32 = 0, kPrecFp64 = 2 };
 // LPN > 1 (FP64 contractions only): LPN lanes share a node, each gathering and storing the
 // x-slabs ix = sub, sub + LPN, ...; the moments are summed across the group and every lane
 // runs the (identical) collision.
-template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1>
+// ADD: the additive collision f* = g + R (a' - a) instead of the rebuild f* = R a' (FP64
+// contractions, one lane per node); g is loaded again at store time.
+template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1, bool ADD = false>
 __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const StepArgs& A,
                                                     const float* __restrict__ fsrc, float* __restrict__ fdst,
                                                     int wb) {
   static_assert(LPN == 1 || PREC == kPrecFp64, "lanes per node > 1 needs the FP64 contractions");
+  static_assert(!ADD || (PREC == kPrecFp64 && LPN == 1), "the additive collision runs with FP64 contractions, one lane");
   constexpr int M = Shape<Q1, N>::M;
   Pull<Q1> P;
   if (!make_pull<Q1, LPN>(L, A, P, wb)) return;
   double d[M];
   double S[5];
+  [[maybe_unused]] double a0[ADD ? M : 1];
   if constexpr (PREC == kPrecFp64) {
     gather_project64<Q1, N, SHOCK, LPN>(L, A, fsrc, P, d);
     sums_from_a<N>(d, L, S);
+    if constexpr (ADD) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) a0[i] = d[i];
+    }
   } else {
     float a[M];
     gather_project<Q1, N, SHOCK>(L, A, fsrc, P, a, S);
@@ -732,7 +802,11 @@ __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const
   to_local<N>(d, mac);
   relax<N>(d, L, mac.rho, mac.tsc);
   to_lattice<N>(d, mac);
-  if constexpr (PREC == kPrecFp64) {
+  if constexpr (ADD) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) d[i] -= a0[i];
+    reconstruct_store64<Q1, N, 1, !SHOCK>(L, d, fdst, A.stride, P.node, 0, PulledSource<Q1, SHOCK>{&L, &A, fsrc, &P});
+  } else if constexpr (PREC == kPrecFp64) {
     reconstruct_store64<Q1, N, LPN, !SHOCK>(L, d, fdst, A.stride, P.node, P.sub);
   } else {
     float ap[M];
@@ -742,10 +816,10 @@ __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const
   }
 }
 
-template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1>
+template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1, bool ADD = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_collide_stream(
     LatticeConst L, StepArgs A, const float* __restrict__ fsrc, float* __restrict__ fdst) {
-  collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, fsrc, fdst, -1);
+  collide_stream_node<Q1, N, SHOCK, PREC, LPN, ADD>(L, A, fsrc, fdst, -1);
 }
 
 // Persistent form: every work-group strides over the block table, n_steps times, with a grid-wide

@@ -55,6 +55,7 @@ struct lbsmrt_ctx {
   int graph_pairs = 0;
   int n_blocks_adj = 0;
   int precision = LBSMRT_FP32;
+  bool additive = false;              // f* = g + R (a' - a) instead of the rebuild (regularized = 0)
   // moment-state form: one periodic domain and a stencil with compile-time taps
   bool ms_ok = false;
   MomentTaps32 ms_k32{};
@@ -84,7 +85,14 @@ template <int Q1, int N>
 struct Launch {
   template <int PREC>
   static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
-    if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
+    // additive collision: FP64 contractions, one lane per node
+    if (PREC == kPrecFp64 && c->additive && c->shock)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0, s,
+                         c->L, A, src, dst);
+    else if (PREC == kPrecFp64 && c->additive)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, false, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0,
+                         s, c->L, A, src, dst);
+    else if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 8>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
                          A, src, dst);
     else if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
@@ -294,8 +302,9 @@ lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
   if (!d) return LBSMRT_E_ARG;
   if (d->n_abscissa < 1 || d->n_abscissa > 8) return LBSMRT_E_ARG;
   if (d->order_N < 2 || d->order_N > kMaxN) return LBSMRT_E_ARG;
-  if (d->regularized != 1) return LBSMRT_E_UNSUPPORTED;
+  if (d->regularized != 0 && d->regularized != 1) return LBSMRT_E_ARG;
   if (d->precision != LBSMRT_FP32 && d->precision != LBSMRT_FP64_CONTRACT) return LBSMRT_E_UNSUPPORTED;
+  if (d->regularized == 0 && d->precision != LBSMRT_FP64_CONTRACT) return LBSMRT_E_UNSUPPORTED;
   if (!(d->rho_ref > 0.0)) return LBSMRT_E_ARG;
   for (int n = 2; n <= d->order_N; ++n)
     for (int m = 0; 2 * m <= n; ++m) {
@@ -353,6 +362,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   c->M = n_moments(c->N);
   c->r = r;
   c->precision = desc->precision;
+  c->additive = desc->regularized == 0;
   for (int j = 0; j < Q1; ++j) {
     const int jj = j - p;  // -p..p
     const int a = jj == 0 ? 0 : (jj < 0 ? -desc->abscissa[-jj - 1] : desc->abscissa[jj - 1]);
@@ -418,7 +428,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   // Shock tubes with few nodes fill a small part of the GPU, and each wavefront's serial work
   // sets the step time: start with several lanes per node there (lbsmrt_set_launch can change it).
   // (the split kernels address a slab by a 32-bit byte offset from the start of f)
-  c->lpn4_ok = c->shock && c->precision == LBSMRT_FP64_CONTRACT &&
+  c->lpn4_ok = c->shock && c->precision == LBSMRT_FP64_CONTRACT && !c->additive &&
                static_cast<long long>(c->Q) * c->stride * 4 < (1LL << 32);
   if (c->lpn4_ok) c->lpn = off * 8 <= kSplitWorkItems ? 8 : (off * 4 <= kSplitWorkItems ? 4 : 1);
   std::vector<BlockDev> bl = block_table(c->doms, c->block / c->lpn);
@@ -452,7 +462,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   // moment-state form (lbsmrt_step_moment_state): K[t][b][a] = He_b(c_t) w_t He_a(c_t)/a! at the
   // non-negative taps t of the stencil
   dispatch(c->Q1, c->N, [&](auto l) { c->ms_ok = decltype(l)::ms_taps_match(c); });
-  c->ms_ok = c->ms_ok && n_domains == 1 && domains[0].bc_x == 0;
+  c->ms_ok = c->ms_ok && n_domains == 1 && domains[0].bc_x == 0 && !c->additive;
   for (int t = 0; t <= p; ++t)
     for (int b = 0; b <= c->N; ++b)
       for (int a = 0; a <= c->N; ++a) {
@@ -593,6 +603,7 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4 && lanes_per_node != 8)
     return LBSMRT_E_ARG;
   if (lanes_per_node > 1 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
+  if (mode == LBSMRT_LAUNCH_PERSISTENT && c->additive) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
   drop_graph(c);
   const int bs = block_size != 0 ? block_size : c->block;
@@ -671,6 +682,7 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* 
                                   double* dL_dtau, void* stream) {
   if (!c || !f_t || !lam_next || !lam_t || !dL_dtau) return LBSMRT_E_ARG;
   if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
+  if (c->additive) return LBSMRT_E_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(stream);
   StepArgs A = step_args(c);
   A.blocks = c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj);

@@ -28,10 +28,12 @@ class Lattice:
     rho_in, u_in, theta_in, rho_out, u_out, theta_out (lab frame).
     precision: "fp64_contract" (default: FP64 contractions, as fast as FP32 ones on gfx950)
     or "fp32" (FP32 contractions); the state is float32 in both.
+    regularized: True (f* rebuilt from the relaxed moments) or False (additive collision
+    f* = g + R (a' - a); FP64 contractions only).
     """
 
     def __init__(self, abscissae, degree, N, tau, domains, shift_k=(0, 0, 0), rho_ref=1.0,
-                 tau_density_scaling=True, tau_offset_half=True, precision="fp64_contract"):
+                 tau_density_scaling=True, tau_offset_half=True, precision="fp64_contract", regularized=True):
         if not torch.cuda.is_available():
             raise RuntimeError("the LB-SMRT library runs on a gfx950 GPU; no GPU is visible")
         lib = C.lib()
@@ -49,7 +51,7 @@ class Lattice:
         d.rho_ref = float(rho_ref)
         d.tau_density_scaling = int(bool(tau_density_scaling))
         d.tau_offset_half = int(bool(tau_offset_half))
-        d.regularized = 1
+        d.regularized = 1 if regularized else 0
         d.precision = {"fp32": C.FP32, "split_bf16x3": C.SPLIT_BF16X3, "fp64_contract": C.FP64_CONTRACT}[precision]
         arr = (C.DomainDesc * len(domains))()
         for i, dom in enumerate(domains):
@@ -65,6 +67,7 @@ class Lattice:
                     x.u_out[k] = float(dom["u_out"][k])
         self.domains = [dict(dm) for dm in domains]
         self.precision = precision
+        self.regularized = bool(regularized)
         self.tau = dict(tau)
         self.shift_k = tuple(int(v) for v in shift_k)
         h = ctypes.c_void_p()
