@@ -245,6 +245,17 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     out[other] = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2)}
     lat2.close()
     _progress(f"{other}: {ms:.3f} ms/step")
+    # additive collision f* = g + R (a' - a): the pulled populations are read twice (12 Q B/node)
+    lat3 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision="fp64_contract",
+                   regularized=False)
+    lat3.step(fa, fb, 2)
+    ms = _time_steps(torch, lambda: lat3.step(fa, fb, 1), steps)
+    lat3.sync()
+    lat3.close()
+    out["additive_collision"] = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2),
+                                 "bytes_per_launch": 12.0 * lat.Q * lat.n_nodes,
+                                 "achieved_GBs": round(12.0 * lat.Q * lat.n_nodes / (ms / 1e3) / 1e9, 1)}
+    _progress(f"additive collision: {ms:.3f} ms/step")
     lam_a, lam_b = lat.new_state(), lat.new_state()
     lam_a.normal_()
     dtau = torch.zeros(18, dtype=torch.float64, device="cuda")

@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--max-steps", type=int, default=400000)
     ap.add_argument("--lanes-per-node", type=int, default=0, choices=[0, 1, 2, 4, 8],
                     help="lanes per node of the step kernel (0: the library's default)")
+    ap.add_argument("--additive", action="store_true",
+                    help="additive collision f* = g + R (a' - a) instead of the rebuild from the moments")
     args = ap.parse_args()
     ab, deg = {"d1q7": ([1, 2, 3], 9), "d1q9": ([1, 2, 3, 5], 11)}[args.stencil]
     theta1 = {1.5: 0.714, 3.0: 0.333, 5.0: 0.167, 7.0: 0.071}.get(args.mach)
@@ -74,7 +76,7 @@ def main():
     dom, fields, _ = shock_domain(args.mach, args.nx, c_l, theta2=st["theta2"])
     k = int(st["k"])
     lat = Lattice(ab, deg, args.order, tau_table(args.tau, 1.0, args.order), [dom], shift_k=(k, 0, 0),
-                  precision="fp64_contract")
+                  precision="fp64_contract", regularized=not args.additive)
     if args.lanes_per_node:
         lat.set_launch("direct", 0, 64, args.lanes_per_node)
     fa = lat.equilibrium(torch.tensor(fields, dtype=torch.float64, device="cuda"))
@@ -88,7 +90,8 @@ def main():
         res["shock_thickness_cells"] = round(shock_thickness(m[0], st), 3)
         res["max_theta"] = round(float(m[4].max()), 4)
         res["min_q_x"] = round(float(m[5].min()), 6)
-    res.update(mach=args.mach, nx=args.nx, tau=args.tau, Q=lat.Q, N=lat.N, k=k, theta1=st["theta1"],
+    res.update(mach=args.mach, nx=args.nx, tau=args.tau, Q=lat.Q, N=lat.N, k=k, additive=args.additive,
+               theta1=st["theta1"],
                theta2=st["theta2"], rho2=st["rho2"], launch=lat.launch_settings())
     print(json.dumps(res), flush=True)
 
