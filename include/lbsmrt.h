@@ -49,9 +49,12 @@ typedef enum {
   LBSMRT_E_STATE = 3,        /* a node left rho > 0, 0 < theta < 2, or became non-finite */
   LBSMRT_E_HIP = 4,          /* a HIP runtime call failed */
   LBSMRT_E_NOMEM = 5,        /* device or host allocation failed */
-  LBSMRT_E_UNSUPPORTED = 6   /* valid but not built: a (Q1, N) pair with no compiled kernel, the
+  LBSMRT_E_UNSUPPORTED = 6   /* valid but not built: a (Q1, N) pair with no compiled kernel (built:
+                                D1Q7 with N = 3, 4; D1Q9 with N = 4, 5; D1Q17 with N = 5), the
                                 reserved precision, regularized = 0 with FP32 contractions (or with
-                                the adjoint, the persistent launch or the moment state), or a launch setting the
+                                the adjoint, the persistent launch or the moment state), D1Q17 with
+                                anything but the forward step, moments and equilibrium in FP64
+                                contractions and the rebuilt collision, or a launch setting the
                                 context does not allow */
 } lbsmrt_status;
 
@@ -67,7 +70,7 @@ typedef struct {
   int    n_abscissa;           /* p: number of positive 1D integers (3 for D1Q7, 4 for D1Q9) */
   int    abscissa[16];         /* sorted distinct positive integers, e.g. {1,2,3} or {1,2,3,5} */
   int    degree;               /* degree of exactness of the 1D rule (9 for D1Q7, 11 for D1Q9) */
-  int    order_N;              /* Hermite truncation N (4 or 5) */
+  int    order_N;              /* Hermite truncation N (3 to 5; see LBSMRT_E_UNSUPPORTED for the pairs) */
   int    shift_k[3];           /* integer frame shift: ubar = c_l * k (Sec. 4.1) */
   double tau[6][3];            /* tau[n][m] in time steps at rho_ref, n = 2..N.  tau[2][1]
                                   is ignored: the (2,1) part vanishes by the definition of theta. */

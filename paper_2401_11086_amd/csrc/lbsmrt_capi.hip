@@ -80,19 +80,28 @@ double hermite_1d(int n, double x) {
   return h1;
 }
 
-// Launch dispatch over the compiled (Q1, N) pairs.
+// Launch dispatch over the compiled (Q1, N) pairs.  The 17-point stencil (kFull false) has the
+// forward step with FP64 contractions and the rebuilt collision, the moments and the equilibrium
+// fill only; the API refuses the rest for it before dispatching.
 template <int Q1, int N>
 struct Launch {
+  static constexpr bool kFull = Q1 <= 9;
   template <int PREC>
   static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
     // additive collision: FP64 contractions, one lane per node
-    if (PREC == kPrecFp64 && c->additive && c->shock)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0, s,
-                         c->L, A, src, dst);
-    else if (PREC == kPrecFp64 && c->additive)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, false, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0,
-                         s, c->L, A, src, dst);
-    else if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
+    if constexpr (kFull) {
+      if (PREC == kPrecFp64 && c->additive && c->shock) {
+        hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0,
+                           s, c->L, A, src, dst);
+        return;
+      }
+      if (PREC == kPrecFp64 && c->additive) {
+        hipLaunchKernelGGL((k_collide_stream<Q1, N, false, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0,
+                           s, c->L, A, src, dst);
+        return;
+      }
+    }
+    if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 8>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
                          A, src, dst);
     else if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
@@ -109,22 +118,31 @@ struct Launch {
                          dst);
   }
   static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
-    if (c->precision == LBSMRT_FP32) step_p<kPrecFp32>(c, A, src, dst, s);
-    else step_p<kPrecFp64>(c, A, src, dst, s);
+    if constexpr (kFull) {
+      if (c->precision == LBSMRT_FP32) {
+        step_p<kPrecFp32>(c, A, src, dst, s);
+        return;
+      }
+    }
+    step_p<kPrecFp64>(c, A, src, dst, s);
   }
   template <int PREC, bool SH>
   static const void* persistent_fn() {
     return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC>);
   }
   static const void* persistent(const lbsmrt_ctx* c) {
-    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8)
-      return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 8>);
-    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
-      return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
-    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2)
-      return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 2>);
-    if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
-    return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
+    if constexpr (!kFull) {
+      return nullptr;
+    } else {
+      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8)
+        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 8>);
+      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
+        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
+      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2)
+        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 2>);
+      if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
+      return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
+    }
   }
   static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s) {
     if (c->shock)
@@ -136,35 +154,39 @@ struct Launch {
   }
   static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
                       hipStream_t s) {
-    const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
-    int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
-    if constexpr (N <= 4) {
-      if (!c->shock && c->n_blocks_adjR > 0) {
-        nb = c->n_blocks_adjR;
-        hipLaunchKernelGGL((k_adjoint<Q1, N, false, 1, kAdjRowBlock>), dim3(nb), dim3(kAdjRowBlock),
-                           2 * sizeof(double) * n_moments(N) * kAdjRowBlock, s, c->L, A, f_t, lam_next, lam_t,
-                           c->d_partial);
-        hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
-                           n_tau_slots(N), c->d_stage);
-        hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
-        return;
+    if constexpr (!kFull) {
+      return;
+    } else {
+      const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
+      int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
+      if constexpr (N <= 4) {
+        if (!c->shock && c->n_blocks_adjR > 0) {
+          nb = c->n_blocks_adjR;
+          hipLaunchKernelGGL((k_adjoint<Q1, N, false, 1, kAdjRowBlock>), dim3(nb), dim3(kAdjRowBlock),
+                             2 * sizeof(double) * n_moments(N) * kAdjRowBlock, s, c->L, A, f_t, lam_next, lam_t,
+                             c->d_partial);
+          hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
+                             n_tau_slots(N), c->d_stage);
+          hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
+          return;
+        }
       }
+      if (c->shock && c->lpn == 8)
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
+                           lam_t, c->d_partial);
+      else if (c->shock && c->lpn == 4)
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
+                           lam_t, c->d_partial);
+      else if (c->shock)
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
+                           lam_t, c->d_partial);
+      else
+        hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
+                           lam_t, c->d_partial);
+      hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
+                         n_tau_slots(N), c->d_stage);
+      hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
     }
-    if (c->shock && c->lpn == 8)
-      hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                         lam_t, c->d_partial);
-    else if (c->shock && c->lpn == 4)
-      hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                         lam_t, c->d_partial);
-    else if (c->shock)
-      hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                         lam_t, c->d_partial);
-    else
-      hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                         lam_t, c->d_partial);
-    hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
-                       n_tau_slots(N), c->d_stage);
-    hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
   }
   // Raise the dynamic LDS limit of the 256-node periodic adjoint (N <= 4); false if refused.
   static bool allow_row_adjoint() {
@@ -177,12 +199,16 @@ struct Launch {
   }
   static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
                         float* lam, hipStream_t s) {
-    if (c->shock)
-      hipLaunchKernelGGL((k_loss_seed<Q1, N, true>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
-                         c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
-    else
-      hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
-                         c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
+    if constexpr (!kFull) {
+      return;
+    } else {
+      if (c->shock)
+        hipLaunchKernelGGL((k_loss_seed<Q1, N, true>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
+                           c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
+      else
+        hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
+                           c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
+    }
   }
   // Moment-state form.  Line chunk of the z and y passes: a multiple of the tap window W, as long
   // as possible (the W - 1 halo rows are read again per chunk) while the launch still has about
@@ -197,28 +223,44 @@ struct Launch {
   }
   static void ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, float* dst, float* t1, float* t2,
                       hipStream_t s) {
-    const long long lz = static_cast<long long>(G.nx) * G.ny, ly = static_cast<long long>(G.nx) * G.nz;
-    const int Tz = ms_chunk(lz, G.nz), Ty = ms_chunk(ly, G.ny);
-    hipLaunchKernelGGL((k_ms_pass_z<Q1, N>), dim3(static_cast<unsigned>((lz + 255) / 256), (G.nz + Tz - 1) / Tz),
-                       dim3(256), 0, s, c->ms_k32, G, src, t1, Tz);
-    hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
-                       dim3(256), 0, s, c->ms_k32, G, t1, t2, Ty);
-    hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
-                       c->ms_k32, G, t2, dst);
+    if constexpr (!kFull) {
+      return;
+    } else {
+      const long long lz = static_cast<long long>(G.nx) * G.ny, ly = static_cast<long long>(G.nx) * G.nz;
+      const int Tz = ms_chunk(lz, G.nz), Ty = ms_chunk(ly, G.ny);
+      hipLaunchKernelGGL((k_ms_pass_z<Q1, N>), dim3(static_cast<unsigned>((lz + 255) / 256), (G.nz + Tz - 1) / Tz),
+                         dim3(256), 0, s, c->ms_k32, G, src, t1, Tz);
+      hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
+                         dim3(256), 0, s, c->ms_k32, G, t1, t2, Ty);
+      hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
+                         c->ms_k32, G, t2, dst);
+    }
   }
   static bool ms_taps_match(const lbsmrt_ctx* c) {
-    const int p = Q1 / 2;
-    for (int t = 0; t <= Taps1D<Q1>::p; ++t)
-      if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
-    return true;
+    if constexpr (!kFull) {
+      return false;
+    } else {
+      const int p = Q1 / 2;
+      for (int t = 0; t <= Taps1D<Q1>::p; ++t)
+        if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
+      return true;
+    }
   }
   static void ms_project(lbsmrt_ctx* c, const float* f, float* m, hipStream_t s) {
-    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-    hipLaunchKernelGGL((k_ms_project<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, f, m, c->stride, c->n_nodes);
+    if constexpr (!kFull) {
+      return;
+    } else {
+      const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+      hipLaunchKernelGGL((k_ms_project<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, f, m, c->stride, c->n_nodes);
+    }
   }
   static void ms_expand(lbsmrt_ctx* c, const float* m, float* f, hipStream_t s) {
-    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-    hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
+    if constexpr (!kFull) {
+      return;
+    } else {
+      const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+      hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
+    }
   }
   static void ms_equilibrium(lbsmrt_ctx* c, const double* fields, float* m, hipStream_t s) {
     const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
@@ -233,7 +275,9 @@ struct Launch {
   }
 };
 
-bool supported(int Q1, int N) { return (Q1 == 7 && (N == 3 || N == 4)) || (Q1 == 9 && (N == 4 || N == 5)); }
+bool supported(int Q1, int N) {
+  return (Q1 == 7 && (N == 3 || N == 4)) || (Q1 == 9 && (N == 4 || N == 5)) || (Q1 == 17 && N == 5);
+}
 
 template <typename F>
 void dispatch(int Q1, int N, F&& fn) {
@@ -241,6 +285,7 @@ void dispatch(int Q1, int N, F&& fn) {
   else if (Q1 == 7 && N == 4) fn(Launch<7, 4>{});
   else if (Q1 == 9 && N == 4) fn(Launch<9, 4>{});
   else if (Q1 == 9 && N == 5) fn(Launch<9, 5>{});
+  else if (Q1 == 17 && N == 5) fn(Launch<17, 5>{});
 }
 
 StepArgs step_args(const lbsmrt_ctx* c) {
@@ -348,6 +393,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   const int p = desc->n_abscissa;
   const int Q1 = 2 * p + 1;
   if (!supported(Q1, desc->order_N)) return LBSMRT_E_UNSUPPORTED;
+  // the 17-point stencil: forward step with FP64 contractions and the rebuilt collision only
+  if (Q1 > 9 && (desc->precision != LBSMRT_FP64_CONTRACT || desc->regularized == 0)) return LBSMRT_E_UNSUPPORTED;
 
   double r = 0.0, w[17] = {};
   st = solve_quadrature(desc->abscissa, p, desc->degree, &r, w);
@@ -463,7 +510,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   // non-negative taps t of the stencil
   dispatch(c->Q1, c->N, [&](auto l) { c->ms_ok = decltype(l)::ms_taps_match(c); });
   c->ms_ok = c->ms_ok && n_domains == 1 && domains[0].bc_x == 0 && !c->additive;
-  for (int t = 0; t <= p; ++t)
+  for (int t = 0; t <= p && t < kMsMaxTaps; ++t)
     for (int b = 0; b <= c->N; ++b)
       for (int a = 0; a <= c->N; ++a) {
         c->ms_k32.K[t][b][a] = static_cast<float>(L.He64[p + t][b] * L.Rw64[p + t][a]);
@@ -603,7 +650,7 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4 && lanes_per_node != 8)
     return LBSMRT_E_ARG;
   if (lanes_per_node > 1 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
-  if (mode == LBSMRT_LAUNCH_PERSISTENT && c->additive) return LBSMRT_E_UNSUPPORTED;
+  if (mode == LBSMRT_LAUNCH_PERSISTENT && (c->additive || c->Q1 > 9)) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
   drop_graph(c);
   const int bs = block_size != 0 ? block_size : c->block;
@@ -626,6 +673,7 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
     const void* fn = nullptr;
     dispatch(c->Q1, c->N, [&](auto l) { fn = decltype(l)::persistent(c); });
     int per_cu = 0, cus = 0;
+    if (!fn) return LBSMRT_E_UNSUPPORTED;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, c->block, 0) != hipSuccess) return LBSMRT_E_HIP;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
       return LBSMRT_E_HIP;
@@ -681,6 +729,7 @@ lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* c, const double* fields, float* f, 
 lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* lam_next, float* lam_t,
                                   double* dL_dtau, void* stream) {
   if (!c || !f_t || !lam_next || !lam_t || !dL_dtau) return LBSMRT_E_ARG;
+  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
   if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
   if (c->additive) return LBSMRT_E_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -695,6 +744,7 @@ lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* 
 lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* c, const float* f, const double* target, const double* scales, float* lam,
                                double* loss, void* stream) {
   if (!c || !f || !target || !scales || !lam || !loss || lam == f) return LBSMRT_E_ARG;
+  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
   hipStream_t s = static_cast<hipStream_t>(stream);
   StepArgs A = step_args(c);
   A.blocks = c->d_blocks_adj;
@@ -736,6 +786,7 @@ lbsmrt_status lbsmrt_equilibrium_moments(lbsmrt_ctx* c, const double* fields, fl
 
 lbsmrt_status lbsmrt_project_state(lbsmrt_ctx* c, const float* f, float* m, void* stream) {
   if (!c || !f || !m) return LBSMRT_E_ARG;
+  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
   const size_t fb = sizeof(float) * c->Q * c->stride, mb = sizeof(float) * c->M * c->stride;
   if (overlap(f, fb, m, mb)) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -745,6 +796,7 @@ lbsmrt_status lbsmrt_project_state(lbsmrt_ctx* c, const float* f, float* m, void
 
 lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* c, const float* m, float* f, void* stream) {
   if (!c || !f || !m) return LBSMRT_E_ARG;
+  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
   const size_t fb = sizeof(float) * c->Q * c->stride, mb = sizeof(float) * c->M * c->stride;
   if (overlap(f, fb, m, mb)) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);

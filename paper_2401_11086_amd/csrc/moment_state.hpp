@@ -39,10 +39,18 @@ struct Taps1D<9> {
   static constexpr int H = 5;
   static constexpr int e[5] = {0, 1, 2, 3, 5};
 };
+template <>
+struct Taps1D<17> {   // D1Q17: no moment-state kernel (more taps than MomentTaps32 holds)
+  static constexpr int p = 8;
+  static constexpr int H = 9;
+  static constexpr int e[9] = {0, 1, 2, 3, 4, 5, 6, 7, 9};
+};
 
-// K[t][b][a] = He_b(c) w He_a(c) / a! at the non-negative tap t (c = r e_t).
+// K[t][b][a] = He_b(c) w He_a(c) / a! at the non-negative tap t (c = r e_t); stencils of up to
+// nine points have a moment-state kernel.
+constexpr int kMsMaxTaps = 5;
 struct MomentTaps32 {
-  float K[kMaxQ1 / 2 + 1][kMaxN + 1][kMaxN + 1];
+  float K[kMsMaxTaps][kMaxN + 1][kMaxN + 1];
 };
 
 struct MsGeom {

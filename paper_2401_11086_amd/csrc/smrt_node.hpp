@@ -18,7 +18,7 @@
 
 namespace lbsmrt {
 
-constexpr int kMaxQ1 = 9;
+constexpr int kMaxQ1 = 17;   // D1Q17 {0, +-1..+-7, +-9} (Table 3, Ma 7)
 constexpr int kMaxN = 5;
 
 __host__ __device__ constexpr int n_moments(int N) { return (N + 1) * (N + 2) * (N + 3) / 6; }

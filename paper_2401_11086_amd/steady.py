@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--mach", type=float, default=3.0)
     ap.add_argument("--nx", type=int, default=1000)
     ap.add_argument("--tau", default="smrt", choices=["smrt", "lumped", "shakhov", "bgk", "reduced"])
-    ap.add_argument("--stencil", default="d1q9", choices=["d1q7", "d1q9"])
+    ap.add_argument("--stencil", default="d1q9", choices=["d1q7", "d1q9", "d1q17"])
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--max-steps", type=int, default=400000)
     ap.add_argument("--lanes-per-node", type=int, default=0, choices=[0, 1, 2, 4, 8],
@@ -69,7 +69,8 @@ def main():
     ap.add_argument("--additive", action="store_true",
                     help="additive collision f* = g + R (a' - a) instead of the rebuild from the moments")
     args = ap.parse_args()
-    ab, deg = {"d1q7": ([1, 2, 3], 9), "d1q9": ([1, 2, 3, 5], 11)}[args.stencil]
+    ab, deg = {"d1q7": ([1, 2, 3], 9), "d1q9": ([1, 2, 3, 5], 11),
+               "d1q17": ([1, 2, 3, 4, 5, 6, 7, 9], 19)}[args.stencil]
     theta1 = {1.5: 0.714, 3.0: 0.333, 5.0: 0.167, 7.0: 0.071}.get(args.mach)
     c_l, _ = C.solve_quadrature(ab, deg)
     st = C.shock_states(args.mach, theta1=theta1 or 0.0, theta2=0.0 if theta1 else 1.07, c_l=c_l)

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(lib):
     assert set(lib.EXPORTED) == set(declared)
 
 
-@pytest.mark.parametrize("ab,deg", [([1, 2, 3], 9), ([1, 2, 3, 5], 11)])
+@pytest.mark.parametrize("ab,deg", [([1, 2, 3], 9), ([1, 2, 3, 5], 11), ([1, 2, 3, 4, 5, 6, 7, 9], 19)])
 def test_library_quadrature_matches_oracle(lib, ab, deg):
     r, w = lib.solve_quadrature(ab, deg)
     ro, wo = O.solve_d1_quadrature(ab, deg)
