@@ -130,4 +130,5 @@ def test_additive_graph_replay_matches_direct(torch):
     lat.set_launch("graph", graph_steps=4)
     b = lat.step(f0.clone(), lat.new_state(), 8)
     lat.sync()
-    assert torch.equal(a, b)
+    n = case["nx"]
+    assert torch.equal(a[:, :n], b[:, :n])     # padding columns are never written
