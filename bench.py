@@ -498,7 +498,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(args.workload, args.precision),
-                     "kernel": f"k_collide_stream<{lat.Q1},{N},false,{2 if args.precision == 'fp64_contract' else 0},1>",
+                     "kernel": f"k_collide_stream<{lat.Q1},{N},false,{2 if args.precision == 'fp64_contract' else 0},1,false>",
                      "bytes_per_launch": bytes_per_launch},
     }
     if variants:
