@@ -7,8 +7,12 @@ FP64 conserved moments / frame shift / relaxation.
 
 Prints one JSON line: MLUPS (interior node updates per second / 1e6), the
 roofline of the step kernel (HBM bound: one FP32 read and one FP32 write of
-every population per node-step = 8 Q bytes), and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+every population per node-step = 8 Q bytes; beside the nominal peak, a plain
+device copy of one state buffer measured in the same run), the FP64 CPU oracle
+timed on a bounded sample of the same workload, and variants of the same box:
+the other contraction precision, the additive collision, the moment-state form
+of the step (state held as the M moments), the adjoint step, the Ma 3 D3Q729
+calibration shock and the batched 64-shock Mach sweep.
 """
 import argparse
 import json
@@ -197,6 +201,15 @@ def device_record(torch):
         except (OSError, IndexError):
             continue
     return rec
+
+
+def copy_ceiling(torch, fa, fb, reps=5):
+    """The HIP runtime's device copy of one state buffer into the other (same buffers, same run):
+    the read + write rate a plain stream reaches on this GPU, beside the step kernel's."""
+    fb.copy_(fa)
+    torch.cuda.synchronize()
+    ms = _time_steps(torch, lambda: fb.copy_(fa), reps)
+    return 2.0 * fa.numel() * 4 / (ms / 1e3) / 1e9
 
 
 def copy_calibration(torch, n_floats, steps, warmup):
@@ -503,6 +516,11 @@ def main():
     }
     if variants:
         out["variants"] = variants
+    # measured streaming ceiling on the same buffers (a plain copy, read + write)
+    ceiling = copy_ceiling(torch, fa, fb)
+    out["roofline"]["copy_GBs_same_buffers"] = round(ceiling, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / ceiling, 4)
+    _progress(f"device copy of one state buffer: {ceiling:.0f} GB/s; step kernel at {achieved / ceiling:.2f} of it")
     if not args.no_cpu_baseline:
         _progress("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(torch, ab, deg, N, edge, args.kn)
