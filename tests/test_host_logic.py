@@ -135,3 +135,21 @@ def test_bench_traffic_record_is_keyed_by_sources(tmp_path, monkeypatch):
     assert bench.recorded_traffic("box256_q343_n4", "fp32") is None
     rec.write_text(rec.read_text().replace(digest, "0" * 64))
     assert bench.recorded_traffic("box256_q343_n4", "fp64_contract") is None
+
+
+def test_truncation_crossing_interpolates():
+    from paper_2401_11086_amd.truncation import _crossing
+    x = np.arange(50, dtype=float)
+    rho_hat = np.clip((x - 10.3) / 20.0, 0.0, 1.0)      # reaches 1/2 at x = 20.3
+    assert _crossing(rho_hat) == pytest.approx(20.3)
+
+
+def test_bench_moment_state_bytes():
+    import bench
+
+    class _L:
+        N, M = 4, 35
+    b = bench.moment_state_bytes(_L)
+    # 35 moment fields and 75 = 5 * 15 intermediate fields per node, FP32
+    assert b == {"pass_z": 4.0 * 110, "pass_y": 8.0 * 75, "pass_x_collide": 4.0 * 110}
+    assert sum(b.values()) == 1480.0
