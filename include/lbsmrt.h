@@ -212,11 +212,15 @@ lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* ctx, const double* tau);
  * order of lbsmrt_moments' LBSMRT_MOM_ALAB rows: by order n, then a, then b descending).
  * lbsmrt_step_moment_state advances it by the same step as lbsmrt_step (pull stream, eq:an
  * projection, SMRT collision), written as a separable convolution of the moment fields
- * along z, y and x; the state moves M floats per node instead of Q.  Results agree with
- * lbsmrt_step on the expanded state up to float32 rounding of m instead of f. */
+ * along z, y and x; the state moves M floats per node instead of Q.  On line domains
+ * (ny = nz = 1: shock tubes, rings) the y and z stages are the identity, because the
+ * quadrature is exact to degree 2N, and the step is the x-stage alone, with the moments of
+ * the fixed end states as ghosts.  Results agree with lbsmrt_step on the expanded state up to
+ * float32 rounding of m instead of f. */
 
 /* Sizes of the moment-state buffers in floats: m_len = M * f_stride (one state) and
- * work_len (scratch of lbsmrt_step_moment_state, 2 (N+1)^2 (N+2)/2 rows of f_stride).
+ * work_len (scratch of lbsmrt_step_moment_state, 2 (N+1)^2 (N+2)/2 rows of f_stride; 0 when
+ * every domain is a line).
  * Either pointer may be NULL.  E_ARG for a NULL ctx. */
 lbsmrt_status lbsmrt_moment_state_len(const lbsmrt_ctx* ctx, long long* m_len, long long* work_len);
 
@@ -236,10 +240,11 @@ lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* ctx, const float* m, float* f, voi
 
 /* Advance a moment state n_steps >= 1 steps; buffers alternate as in lbsmrt_step (result in
  * m_a for even n_steps, in m_b for odd).  work: lbsmrt_moment_state_len's work_len floats of
- * caller-owned device memory, contents irrelevant; none of m_a, m_b, work may overlap.
- * E_UNSUPPORTED unless the context has exactly one periodic domain (bc_x = 0) and the
- * stencil is D1Q7 {0, +-1, +-2, +-3} or D1Q9 {0, +-1, +-2, +-3, +-5}.  Validity failures
- * latch the flag read by lbsmrt_sync_status.  Asynchronous. */
+ * caller-owned device memory, contents irrelevant (unused, may be NULL, when every domain is a
+ * line); none of m_a, m_b, work may overlap.  E_UNSUPPORTED unless the context has exactly one
+ * periodic domain (bc_x = 0) or only line domains (ny = nz = 1, any bc_x, any number), the
+ * rebuilt collision, and the stencil D1Q7 {0, +-1, +-2, +-3} or D1Q9 {0, +-1, +-2, +-3, +-5}.
+ * Validity failures latch the flag read by lbsmrt_sync_status.  Asynchronous. */
 lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* ctx, float* m_a, float* m_b, float* work, int n_steps,
                                        void* stream);
 

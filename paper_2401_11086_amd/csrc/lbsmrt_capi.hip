@@ -56,8 +56,11 @@ struct lbsmrt_ctx {
   int n_blocks_adj = 0;
   int precision = LBSMRT_FP32;
   bool additive = false;              // f* = g + R (a' - a) instead of the rebuild (regularized = 0)
-  // moment-state form: one periodic domain and a stencil with compile-time taps
+  // moment-state form: one periodic domain (box passes) or line domains only (ny = nz = 1: the
+  // x-stage alone), with a stencil whose taps are compiled
   bool ms_ok = false;
+  bool ms_lines = false;
+  float* d_ghost_m = nullptr;        // [M][n_ghost] moments of the end states (line domains)
   MomentTaps32 ms_k32{};
 };
 
@@ -236,6 +239,18 @@ struct Launch {
                          c->ms_k32, G, t2, dst);
     }
   }
+  static void ms_line_step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
+    if constexpr (!kFull) {
+      return;
+    } else {
+      if (c->shock)
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true>), dim3(c->n_blocks_adj), dim3(kAdjBlock), 0, s, c->L,
+                           c->ms_k32, A, c->d_ghost_m, src, dst);
+      else
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false>), dim3(c->n_blocks_adj), dim3(kAdjBlock), 0, s, c->L,
+                           c->ms_k32, A, c->d_ghost_m, src, dst);
+    }
+  }
   static bool ms_taps_match(const lbsmrt_ctx* c) {
     if constexpr (!kFull) {
       return false;
@@ -261,6 +276,11 @@ struct Launch {
       const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
       hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
     }
+  }
+  static void ms_equilibrium_into(lbsmrt_ctx* c, const double* fields, long long count, float* m, long long stride,
+                                  hipStream_t s) {
+    const unsigned nb = static_cast<unsigned>((count + 255) / 256);
+    hipLaunchKernelGGL((k_ms_equilibrium<N>), dim3(nb), dim3(256), 0, s, c->L, fields, count, m, stride);
   }
   static void ms_equilibrium(lbsmrt_ctx* c, const double* fields, float* m, hipStream_t s) {
     const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
@@ -320,6 +340,7 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_blocks_adj8);
   (void)hipFree(c->d_blocks_adjR);
   (void)hipFree(c->d_stage);
+  (void)hipFree(c->d_ghost_m);
   delete c;
 }
 
@@ -509,7 +530,10 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   // moment-state form (lbsmrt_step_moment_state): K[t][b][a] = He_b(c_t) w_t He_a(c_t)/a! at the
   // non-negative taps t of the stencil
   dispatch(c->Q1, c->N, [&](auto l) { c->ms_ok = decltype(l)::ms_taps_match(c); });
-  c->ms_ok = c->ms_ok && n_domains == 1 && domains[0].bc_x == 0 && !c->additive;
+  bool lines = true;
+  for (int i = 0; i < n_domains; ++i) lines = lines && domains[i].ny == 1 && domains[i].nz == 1;
+  c->ms_lines = c->ms_ok && lines && !c->additive;
+  c->ms_ok = c->ms_ok && !c->additive && (lines || (n_domains == 1 && domains[0].bc_x == 0));
   for (int t = 0; t <= p && t < kMsMaxTaps; ++t)
     for (int b = 0; b <= c->N; ++b)
       for (int a = 0; a <= c->N; ++a) {
@@ -533,6 +557,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (!blaR.empty() && hipMalloc(&c->d_blocks_adjR, sizeof(BlockDev) * blaR.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_stage, sizeof(double) * kTauCols * kReduceBlocks) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+  if (c->ms_lines && hipMalloc(&c->d_ghost_m, sizeof(float) * c->M * c->n_ghost) != hipSuccess)
+    return fail(LBSMRT_E_NOMEM);
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
   std::vector<double> gf(5 * c->n_ghost, 0.0);
   for (int i = 0; i < n_domains; ++i) {
@@ -562,6 +588,10 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       hipMemsetAsync(c->d_err, 0, sizeof(int), s) != hipSuccess)
     return fail(LBSMRT_E_HIP);
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::equilibrium(c, c->d_ghost_fields, c->n_ghost, c->d_ghost, c->n_ghost, s); });
+  if (c->ms_lines)   // moments of the end states, [M][n_ghost]
+    dispatch(c->Q1, c->N, [&](auto l) {
+      decltype(l)::ms_equilibrium_into(c, c->d_ghost_fields, c->n_ghost, c->d_ghost_m, c->n_ghost, s);
+    });
   if (hipGetLastError() != hipSuccess) return fail(LBSMRT_E_HIP);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(LBSMRT_E_HIP);
   *out = c;
@@ -773,7 +803,7 @@ lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* c, const double* tau) {
 lbsmrt_status lbsmrt_moment_state_len(const lbsmrt_ctx* c, long long* m_len, long long* work_len) {
   if (!c) return LBSMRT_E_ARG;
   if (m_len) *m_len = static_cast<long long>(c->M) * c->stride;
-  if (work_len) *work_len = 2LL * n_sym(c->N) * (c->N + 1) * c->stride;
+  if (work_len) *work_len = c->ms_lines ? 0 : 2LL * n_sym(c->N) * (c->N + 1) * c->stride;
   return LBSMRT_OK;
 }
 
@@ -806,14 +836,25 @@ lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* c, const float* m, float* f, void*
 
 lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* c, float* m_a, float* m_b, float* work, int n_steps,
                                        void* stream) {
-  if (!c || !m_a || !m_b || !work || n_steps < 1) return LBSMRT_E_ARG;
+  if (!c || !m_a || !m_b || n_steps < 1) return LBSMRT_E_ARG;
   if (!c->ms_ok) return LBSMRT_E_UNSUPPORTED;
+  if (!c->ms_lines && !work) return LBSMRT_E_ARG;
   const size_t mb = sizeof(float) * c->M * c->stride;
   const size_t half = static_cast<size_t>(n_sym(c->N)) * (c->N + 1) * c->stride;   // floats per intermediate
-  if (overlap(m_a, mb, m_b, mb) || overlap(m_a, mb, work, 2 * half * sizeof(float)) ||
-      overlap(m_b, mb, work, 2 * half * sizeof(float)))
+  if (overlap(m_a, mb, m_b, mb)) return LBSMRT_E_ARG;
+  if (!c->ms_lines && (overlap(m_a, mb, work, 2 * half * sizeof(float)) || overlap(m_b, mb, work, 2 * half * sizeof(float))))
     return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->ms_lines) {
+    StepArgs A = step_args(c);
+    A.blocks = c->d_blocks_adj;
+    for (int t = 0; t < n_steps; ++t) {
+      const float* src = (t & 1) ? m_b : m_a;
+      float* dst = (t & 1) ? m_a : m_b;
+      dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_line_step(c, A, src, dst, s); });
+    }
+    return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+  }
   const lbsmrt_domain& D = c->doms[0];
   MsGeom G;
   G.nx = D.nx; G.ny = D.ny; G.nz = D.nz;

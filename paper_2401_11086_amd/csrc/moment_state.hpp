@@ -276,6 +276,129 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
   for (int i = 0; i < M; ++i) store_at(m_out + static_cast<size_t>(i) * G.stride, off, static_cast<float>(d[i]));
 }
 
+// ------------------------------------------------------------------ line domains
+// A domain with ny = nz = 1 (a shock tube, or a periodic ring): every y and z tap pulls from the
+// node itself, and sum_e K_{b a}(e) = sum_j He_b(c_j) w_j He_a(c_j) / a! is the Kronecker delta
+// for a, b <= N (the quadrature is exact to degree 2N), so passes z and y are the identity and
+// the step is the x-stage on the moment fields themselves, followed by the collision.  Pulls
+// from beyond a shock tube's ends read the moments of its fixed end states.
+
+// Sources of the x taps of one node: byte offset into a moment row, or a ghost column.
+template <int Q1>
+struct LineTaps {
+  unsigned op[Taps1D<Q1>::p + 1], om[Taps1D<Q1>::p + 1];   // tap +e_t, tap -e_t
+  int gp[Taps1D<Q1>::p + 1], gm[Taps1D<Q1>::p + 1];         // -1 inside, else the ghost column
+};
+
+template <int Q1, int N, bool SHOCK, int BY, int BZ>
+__device__ __forceinline__ void line_group(const MomentTaps32& K, const float* __restrict__ src, long long stride,
+                                           const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                           const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
+  using S = Taps1D<Q1>;
+  constexpr int NO = N - BY - BZ;
+  float acc[NO + 1];
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.f;
+#pragma unroll
+  for (int a = 0; a <= NO; ++a) {
+    const int field = midx(a, BY, BZ);
+    const float* __restrict__ row = src + static_cast<size_t>(field) * stride;
+    auto tap = [&](unsigned off, int g) {
+      float v = load_at(row, off);
+      if (SHOCK && any_ghost) {
+        const float gv = ghost_m[static_cast<size_t>(field) * n_ghost + (g < 0 ? 0 : g)];
+        v = g < 0 ? v : gv;
+      }
+      return v;
+    };
+    if (!(a & 1)) {
+      const float c = tap(T.op[0], T.gp[0]);
+#pragma unroll
+      for (int b = 0; b <= NO; b += 2) acc[b] = fmaf(K.K[0][b][a], c, acc[b]);
+    }
+#pragma unroll
+    for (int t = 1; t <= S::p; ++t) {
+      const float vp = tap(T.op[t], T.gp[t]);
+      const float vm = tap(T.om[t], T.gm[t]);
+      const float s = vp + vm, dd = vp - vm;
+#pragma unroll
+      for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
+    }
+  }
+  // as in pass x: pin the sums before the next group's loads
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) {
+    asm volatile("" : "+v"(acc[b]));
+    a32[midx(b, BY, BZ)] = acc[b];
+  }
+  asm volatile("" ::: "memory");
+}
+
+template <int Q1, int N, bool SHOCK, int BY, int BZ>
+__device__ __forceinline__ void line_groups(const MomentTaps32& K, const float* __restrict__ src, long long stride,
+                                            const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                            const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
+  if constexpr (BY <= N) {
+    if constexpr (BY + BZ <= N) {
+      line_group<Q1, N, SHOCK, BY, BZ>(K, src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+      line_groups<Q1, N, SHOCK, BY, BZ + 1>(K, src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+    } else {
+      line_groups<Q1, N, SHOCK, BY + 1, 0>(K, src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+    }
+  }
+}
+
+// One node of a line domain per work-item; work-groups are the 64-node blocks of the block table
+// (any number of line domains, each of its own length and end states).  ghost_m: float32
+// [M][n_ghost] moments of the end states (columns 2 d, 2 d + 1 for domain d).
+template <int Q1, int N, bool SHOCK>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_line_collide(LatticeConst L, MomentTaps32 K, StepArgs A,
+                                                        const float* __restrict__ ghost_m,
+                                                        const float* __restrict__ src, float* __restrict__ dst) {
+  using S = Taps1D<Q1>;
+  constexpr int M = n_moments(N);
+  const BlockDev bd = A.blocks[blockIdx.x];
+  const DomainDev D = A.doms[bd.dom];
+  const int x = bd.first + static_cast<int>(threadIdx.x);
+  if (x >= D.nx) return;
+  const int row0 = static_cast<int>(D.off);
+  LineTaps<Q1> T;
+  bool ghost = false;
+  auto source = [&](int xs, unsigned& off, int& g) {
+    g = -1;
+    if (D.bc_x == 0) {
+      xs %= D.nx;
+      if (xs < 0) xs += D.nx;
+    } else if (xs < 0 || xs >= D.nx) {
+      g = D.ghost + (xs < 0 ? 0 : 1);
+      ghost = true;
+      xs = x;                                   // an in-domain address; the ghost value replaces it
+    }
+    off = static_cast<unsigned>(row0 + xs) * 4u;
+  };
+#pragma unroll
+  for (int t = 0; t <= S::p; ++t) {
+    source(x - S::e[t] - L.k[0], T.op[t], T.gp[t]);
+    source(x + S::e[t] - L.k[0], T.om[t], T.gm[t]);
+  }
+  const bool any_ghost = SHOCK && __any(ghost);
+  float a32[M];
+  line_groups<Q1, N, SHOCK, 0, 0>(K, src, A.stride, ghost_m, A.n_ghost, any_ghost, T, a32);
+  double d[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
+  double S5[5];
+  sums_from_a<N>(d, L, S5);
+  Macro mac = macro_from_sums(L, S5, A.err);
+  mac.tsc = D.tau_scale;
+  to_local<N>(d, mac);
+  relax<N>(d, L, mac.rho, mac.tsc);
+  to_lattice<N>(d, mac);
+  const unsigned off = static_cast<unsigned>(row0 + x) * 4u;
+#pragma unroll
+  for (int i = 0; i < M; ++i) store_at(dst + static_cast<size_t>(i) * A.stride, off, static_cast<float>(d[i]));
+}
+
 // Own-node projection of a population state: m[alpha] = sum_i f_i He_alpha(c_i) (FP64 sums).
 template <int Q1, int N>
 __global__ __launch_bounds__(256) void k_ms_project(LatticeConst L, const float* __restrict__ f,

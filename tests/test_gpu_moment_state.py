@@ -155,6 +155,7 @@ def test_moment_state_rejects_unsupported_contexts(torch):
     from paper_2401_11086_amd.shocks import shock_domain
     c_l, _ = C.solve_quadrature([1, 2, 3], 9)
     dom, _, _ = shock_domain(1.2, 40, c_l)
+    dom["ny"] = 2                         # a shock tube two nodes wide: neither a line nor a box
     tau = {(2, 0): 1.0, (3, 0): 1.0, (3, 1): 1.0, (4, 0): 1.0, (4, 1): 1.0, (4, 2): 1.0}
     shock = Lattice([1, 2, 3], 9, 4, tau, [dom], shift_k=(1, 0, 0))
     m, mb, w = shock.new_moment_state(), shock.new_moment_state(), shock.new_moment_work()
@@ -201,3 +202,97 @@ def test_full_size_box_one_step_matches_population_step(torch):
     err = worst / scale
     print(f"256^3 one step: moment state vs population state {err:.2e}")
     assert err < TOL_STEP, err
+
+
+# ---- line domains (ny = nz = 1): the x-stage alone, end states as ghosts ---------------------
+
+def _line_lattice(domains, stencil, N, shift):
+    from paper_2401_11086_amd import Lattice
+    ab, deg = stencil
+    vs = O.make_velocity_set(ab, deg)
+    tau20 = 2.0 * vs.r / 0.6
+    tau = {key: float(v) * tau20 for key, v in O.TAU_STAR_SMRT.items() if key[0] <= N}
+    return Lattice(ab, deg, N, tau, domains, shift_k=shift, precision="fp64_contract")
+
+
+def _shock_domains(machs_lengths, stencil):
+    from paper_2401_11086_amd import _lib as C
+    from paper_2401_11086_amd.shocks import shock_domain
+    c_l, _ = C.solve_quadrature(*stencil)
+    doms, fields, ks = [], [], []
+    for Ma, nx in machs_lengths:
+        d, fl, st = shock_domain(Ma, nx, c_l)
+        doms.append(d)
+        fields.append(fl)
+        ks.append(int(st["k"]))
+    return doms, np.concatenate(fields, axis=1), ks
+
+
+LINE_CASES = [
+    ("shock_q343_n4_ma1.2", D1Q7, 4, [(1.2, 200)]),
+    ("shock_q729_n5_ma3", D1Q9, 5, [(3.0, 120)]),
+    ("batch3_q729_n5", D1Q9, 5, [(1.5, 90), (3.0, 130), (2.2, 70)]),
+    ("ring_q343_n4", D1Q7, 4, None),
+]
+
+
+def _line_case(stencil, N, spec):
+    if spec is None:                                  # periodic ring of 50 nodes
+        doms = [dict(nx=50, ny=1, nz=1, bc_x=0)]
+        lat = _line_lattice(doms, stencil, N, (0, 0, 0))
+        return lat, _fields((50, 1, 1), (0, 0, 0), lat.c_l, seed=31)
+    doms, fields, ks = _shock_domains(spec, stencil)
+    assert len(set(ks)) == 1
+    return _line_lattice(doms, stencil, N, (ks[0], 0, 0)), fields
+
+
+@pytest.mark.parametrize("name,stencil,N,spec", LINE_CASES, ids=[c[0] for c in LINE_CASES])
+def test_line_moment_state_matches_population_step(torch, name, stencil, N, spec):
+    lat, fields = _line_case(stencil, N, spec)
+    n = lat.n_nodes
+    assert lat.moment_state_len()[1] == 0           # line domains need no scratch
+    m0 = _noisy_moments(torch, lat, fields, seed=32)
+    f0 = lat.expand_state(m0)
+    steps = 5
+    f_pop = lat.step(f0.clone(), lat.new_state(), steps)
+    m_out = lat.step_moment_state(m0, lat.new_moment_state(), lat.new_moment_work(), steps)
+    lat.sync()
+    f_mom = lat.expand_state(m_out)
+    torch.cuda.synchronize()
+    a, b = f_mom[:, :n].double(), f_pop[:, :n].double()
+    err = float((a - b).abs().max() / b.abs().max())
+    print(f"{name}: {steps} steps, line moment state vs population state {err:.2e}")
+    assert err < TOL_STEP, err
+
+
+def test_line_moment_state_one_step_matches_oracle(torch):
+    from cases import oracle_state_from_gpu, shock_case
+    case = shock_case(3.0, 64, D1Q9, 5)
+    from paper_2401_11086_amd import Lattice
+    lat = Lattice(precision="fp64_contract", **case["lat_kw"])
+    m0 = _noisy_moments(torch, lat, case["fields"], seed=33)
+    f0 = lat.expand_state(m0)
+    m1 = lat.step_moment_state(m0, lat.new_moment_state(), lat.new_moment_work(), 1)
+    lat.sync()
+    g = lat.expand_state(m1)[:, :64].double().cpu().numpy()
+    fo1 = O.step(oracle_state_from_gpu(f0.cpu().numpy(), case), case["model"], case["dom"])
+    err = float(np.abs(g - fo1.reshape(g.shape)).max() / np.abs(fo1).max())
+    print(f"Ma 3 shock, one line moment-state step vs FP64 oracle: {err:.2e}")
+    assert err < TOL_STEP, err
+
+
+def test_line_batch_equals_separate_contexts(torch):
+    spec = [(1.5, 90), (3.0, 130), (2.2, 70)]
+    lat, fields = _line_case(D1Q9, 5, spec)
+    m0 = _noisy_moments(torch, lat, fields, seed=34)
+    mb = lat.step_moment_state(m0.clone(), lat.new_moment_state(), lat.new_moment_work(), 7)
+    lat.sync()
+    off = 0
+    for i, (Ma, nx) in enumerate(spec):
+        one, fl = _line_case(D1Q9, 5, [(Ma, nx)])
+        m1 = one.new_moment_state()
+        m1[:, :nx] = m0[:, off:off + nx]
+        out = one.step_moment_state(m1, one.new_moment_state(), one.new_moment_work(), 7)
+        one.sync()
+        assert torch.equal(out[:, :nx], mb[:, off:off + nx]), i
+        off += nx
