@@ -341,6 +341,9 @@ def time_shock_adjoint(torch, steps=300):
     fb = lat.new_state()
     lat.step(fa, fb, 10)
     ms_fwd = _time_steps(torch, lambda: lat.step(fa, fb, 1), steps)
+    ma, mb, work = lat.project_state(fa), lat.new_moment_state(), lat.new_moment_work()
+    lat.step_moment_state(ma, mb, work, 10)
+    ms_mom = _time_steps(torch, lambda: lat.step_moment_state(ma, mb, work, 1), steps)
     lam_a, lam_b = lat.new_state(), lat.new_state()
     lam_a.normal_()
     dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
@@ -349,8 +352,10 @@ def time_shock_adjoint(torch, steps=300):
     lat.sync()
     assert torch.isfinite(dtau).all()
     lat.close()
-    _progress(f"shock adjoint (Nx 600, D3Q729): forward {ms_fwd * 1e3:.1f} us, adjoint {ms_adj * 1e3:.1f} us")
+    _progress(f"shock adjoint (Nx 600, D3Q729): forward {ms_fwd * 1e3:.1f} us (moment state {ms_mom * 1e3:.1f} us), "
+              f"adjoint {ms_adj * 1e3:.1f} us")
     return {"workload": "Ma 3 shock, Nx 600, D3Q729, N=5, FP64 contractions", "forward_us": round(ms_fwd * 1e3, 2),
+            "forward_moment_state_us": round(ms_mom * 1e3, 2),
             "adjoint_us": round(ms_adj * 1e3, 2), "ratio_to_forward": round(ms_adj / ms_fwd, 3)}
 
 
@@ -391,6 +396,19 @@ def time_batched(torch, n_shocks=64, steps=5000, seed=0):
            "autotune_trials": tune.get("trials")}
     _progress(f"batched sweep: {ms * 1e3:.1f} us/step ({tune['mode']}, {tune['block']}, "
               f"{tune['lanes_per_node']} lanes/node)")
+    # the same batch with its state held as moments (line domains: the x-stage alone)
+    ma = lat.project_state(f0)
+    mb = lat.new_moment_state()
+    work = lat.new_moment_work()
+    lat.step_moment_state(ma, mb, work, 2)
+    lat.sync()
+    ms_m = _time_steps(torch, lambda: lat.step_moment_state(ma, mb, work, steps), 1) / steps
+    lat.sync()
+    out["batched_moment_state"] = {"ms_per_step": round(ms_m, 5), "mlups": round(nodes / (ms_m / 1e3) / 1e6, 1),
+                                   "bytes_per_node_step": 8.0 * lat.M,
+                                   "speedup_vs_population_batch": round(ms / ms_m, 2)}
+    _progress(f"batched sweep, moment state: {ms_m * 1e3:.1f} us/step")
+    del ma, mb
     # the same shocks as separate contexts, one launch per shock per step
     sep = []
     for d, f in zip(doms, fields):
