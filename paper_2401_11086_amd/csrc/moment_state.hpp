@@ -290,6 +290,20 @@ struct LineTaps {
   int gp[Taps1D<Q1>::p + 1], gm[Taps1D<Q1>::p + 1];         // -1 inside, else the ghost column
 };
 
+// Groups (by, bz) in their compile-time order: index of (BY, BZ).
+constexpr int group_index(int N, int BY, int BZ) {
+  int g = 0;
+  for (int by = 0; by < BY; ++by) g += N - by + 1;
+  return g + BZ;
+}
+
+// Groups whose loads may be in flight together in the line kernel (a memory fence after every
+// kLineGroupsPerPhase groups): fewer serial load round trips per node, more registers.
+#ifndef LBSMRT_LINE_GROUPS_PER_PHASE
+#define LBSMRT_LINE_GROUPS_PER_PHASE 3
+#endif
+constexpr int kLineGroupsPerPhase = LBSMRT_LINE_GROUPS_PER_PHASE;
+
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
 __device__ __forceinline__ void line_group(const MomentTaps32& K, const float* __restrict__ src, long long stride,
                                            const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
@@ -325,13 +339,13 @@ __device__ __forceinline__ void line_group(const MomentTaps32& K, const float* _
       for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
     }
   }
-  // as in pass x: pin the sums before the next group's loads
+  // as in pass x: pin the sums, and fence the loads after every kLineGroupsPerPhase groups
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
     asm volatile("" : "+v"(acc[b]));
     a32[midx(b, BY, BZ)] = acc[b];
   }
-  asm volatile("" ::: "memory");
+  if constexpr ((group_index(N, BY, BZ) + 1) % kLineGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
