@@ -180,6 +180,20 @@ __global__ __launch_bounds__(256) void k_ms_pass_y(MomentTaps32 K, MsGeom G, con
     }
 }
 
+// Groups (by, bz) in their compile-time order: index of (BY, BZ).
+constexpr int group_index(int N, int BY, int BZ) {
+  int g = 0;
+  for (int by = 0; by < BY; ++by) g += N - by + 1;
+  return g + BZ;
+}
+
+// Groups whose loads may be in flight together in pass x and the line kernel (a memory fence
+// after every kGroupsPerPhase groups): fewer serial load round trips per node, more registers.
+#ifndef LBSMRT_GROUPS_PER_PHASE
+#define LBSMRT_GROUPS_PER_PHASE 3
+#endif
+constexpr int kGroupsPerPhase = LBSMRT_GROUPS_PER_PHASE;
+
 // One (by, bz) group of pass x: a[bx, by, bz] = sum_ax sum_e K_{bx ax}(e) t2[ax, by, bz](x - e - k_x)
 // for bx <= N - by - bz (FP32 sums, taps folded over +-e).
 template <int Q1, int N, int BY, int BZ>
@@ -209,14 +223,15 @@ __device__ __forceinline__ void x_group(const MomentTaps32& K, const float* __re
       for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
     }
   }
-  // Finish each group before the next one's loads: the empty asm statements pin the sums here
-  // and order the loads, otherwise every loaded value stays live until the collision.
+  // Finish each group before later loads: the empty asm statements pin the sums here and fence
+  // the loads every kGroupsPerPhase groups, otherwise every loaded value stays live until the
+  // collision.
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
     asm volatile("" : "+v"(acc[b]));
     a32[midx(b, BY, BZ)] = acc[b];
   }
-  asm volatile("" ::: "memory");
+  if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
 // All groups (by, bz), by + bz <= N, in compile-time order.
@@ -290,20 +305,6 @@ struct LineTaps {
   int gp[Taps1D<Q1>::p + 1], gm[Taps1D<Q1>::p + 1];         // -1 inside, else the ghost column
 };
 
-// Groups (by, bz) in their compile-time order: index of (BY, BZ).
-constexpr int group_index(int N, int BY, int BZ) {
-  int g = 0;
-  for (int by = 0; by < BY; ++by) g += N - by + 1;
-  return g + BZ;
-}
-
-// Groups whose loads may be in flight together in the line kernel (a memory fence after every
-// kLineGroupsPerPhase groups): fewer serial load round trips per node, more registers.
-#ifndef LBSMRT_LINE_GROUPS_PER_PHASE
-#define LBSMRT_LINE_GROUPS_PER_PHASE 3
-#endif
-constexpr int kLineGroupsPerPhase = LBSMRT_LINE_GROUPS_PER_PHASE;
-
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
 __device__ __forceinline__ void line_group(const MomentTaps32& K, const float* __restrict__ src, long long stride,
                                            const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
@@ -339,13 +340,13 @@ __device__ __forceinline__ void line_group(const MomentTaps32& K, const float* _
       for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
     }
   }
-  // as in pass x: pin the sums, and fence the loads after every kLineGroupsPerPhase groups
+  // as in pass x: pin the sums, and fence the loads after every kGroupsPerPhase groups
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
     asm volatile("" : "+v"(acc[b]));
     a32[midx(b, BY, BZ)] = acc[b];
   }
-  if constexpr ((group_index(N, BY, BZ) + 1) % kLineGroupsPerPhase == 0) asm volatile("" ::: "memory");
+  if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
