@@ -132,11 +132,39 @@ def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
             "f_max_scaled": float(np.abs(g - ref).max() / np.abs(ref).max()),
             "rho_max_abs": float(np.abs(ob["rho"] - ob_ref["rho"]).max()),
             "theta_max_abs": float(np.abs(ob["theta"] - ob_ref["theta"]).max())}
+    # the same oracle on one thread, a few steps from the same state
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        f1 = f32.astype(np.float64).reshape(vs.Q, sample_edge, sample_edge, sample_edge)
+        one_steps = 3
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            for _ in range(one_steps):
+                f1 = O.step(f1, model, dom)
+            dt1 = time.perf_counter() - t1
+        single = {"value": round(n * one_steps / dt1 / 1e6, 6), "unit": "MLUPS", "cores": 1,
+                  "sample": f"{sample_edge}^3 box, {one_steps} steps, {dt1:.1f} s"}
+    except ImportError:
+        pass
     return {"value": round(n * steps / dt / 1e6, 6), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{sample_edge}^3 periodic box of the same Fourier workload, {steps} steps, "
                       f"{dt:.1f} s; numpy FP64 with {threads} BLAS threads",
+            "cpu_model": cpu_model(), "single_thread": single,
             "gpu_error_vs_oracle": errors}
+
+
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def shock_samples(torch):
