@@ -62,7 +62,6 @@ __host__ __device__ constexpr double multiplicity(int a, int b, int c) {
 template <int N, class V>
 __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro& mac, const V& dv, const V& zv,
                                              double* ab, double* tb) {
-  constexpr int M = n_moments(N);
   const double rho = mac.rho, th = mac.th;
   const double u[3] = {mac.ux, mac.uy, mac.uz};
   const double sc = mac.tsc * (L.density_scaling ? L.rho_ref / rho : 1.0);
