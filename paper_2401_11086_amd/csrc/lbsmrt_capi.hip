@@ -239,16 +239,28 @@ struct Launch {
                          c->ms_k32, G, t2, dst);
     }
   }
-  static void ms_line_step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
+  // Line domains: eight lanes per node (one tap pair each) when the context splits nodes over
+  // four or more lanes (small tubes), else one.
+  static void ms_line_step(lbsmrt_ctx* c, const StepArgs& A0, const float* src, float* dst, hipStream_t s) {
     if constexpr (!kFull) {
       return;
     } else {
-      if (c->shock)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true>), dim3(c->n_blocks_adj), dim3(kAdjBlock), 0, s, c->L,
-                           c->ms_k32, A, c->d_ghost_m, src, dst);
+      StepArgs A = A0;
+      const bool split = c->lpn >= 4;
+      A.blocks = split ? c->d_blocks_adj8 : c->d_blocks_adj;
+      const int nb = split ? c->n_blocks_adj8 : c->n_blocks_adj;
+      if (split && c->shock)
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+                           c->d_ghost_m, src, dst);
+      else if (split)
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+                           c->d_ghost_m, src, dst);
+      else if (c->shock)
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+                           c->d_ghost_m, src, dst);
       else
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false>), dim3(c->n_blocks_adj), dim3(kAdjBlock), 0, s, c->L,
-                           c->ms_k32, A, c->d_ghost_m, src, dst);
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+                           c->d_ghost_m, src, dst);
     }
   }
   static bool ms_taps_match(const lbsmrt_ctx* c) {
@@ -846,8 +858,7 @@ lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* c, float* m_a, float* m_b, fl
     return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (c->ms_lines) {
-    StepArgs A = step_args(c);
-    A.blocks = c->d_blocks_adj;
+    const StepArgs A = step_args(c);
     for (int t = 0; t < n_steps; ++t) {
       const float* src = (t & 1) ? m_b : m_a;
       float* dst = (t & 1) ? m_a : m_b;

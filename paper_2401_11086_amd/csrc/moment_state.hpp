@@ -363,21 +363,103 @@ __device__ __forceinline__ void line_groups(const MomentTaps32& K, const float* 
   }
 }
 
-// One node of a line domain per work-item; work-groups are the 64-node blocks of the block table
-// (any number of line domains, each of its own length and end states).  ghost_m: float32
-// [M][n_ghost] moments of the end states (columns 2 d, 2 d + 1 for domain d).
-template <int Q1, int N, bool SHOCK>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_line_collide(LatticeConst L, MomentTaps32 K, StepArgs A,
-                                                        const float* __restrict__ ghost_m,
-                                                        const float* __restrict__ src, float* __restrict__ dst) {
+// Lanes per node in the line kernel: lane `sub` of a node's group takes the tap pair e_sub of the
+// x-stage (the centre for sub = 0, nothing for sub > p) for every group, and the group sums the
+// partial moments with DPP moves inside each row (as the population kernel does), so every
+// lane holds the same sums and runs the same collision.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+template <int LPN, int M>
+__device__ __forceinline__ void group_allreduce_f32(float (&a)[M]) {
+  static_assert(LPN == 4 || LPN == 8, "groups of 4 or 8 lanes");
+  constexpr int kSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
+  constexpr int kSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
+  constexpr int kHalfMirror = 0x141;                            // row_half_mirror
+#pragma unroll
+  for (int i = 0; i < M; ++i) a[i] += dpp_move_f32<kSwap1>(a[i]);
+#pragma unroll
+  for (int i = 0; i < M; ++i) a[i] += dpp_move_f32<kSwap2>(a[i]);
+  if constexpr (LPN == 8) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) a[i] += dpp_move_f32<kHalfMirror>(a[i]);
+  }
+}
+
+// One lane's tap pair: sources of +e and -e (or the centre), and its 1D table K[t][b][a].
+template <int N>
+struct LaneTap {
+  unsigned op, om;
+  int gp, gm;
+  bool pair;                          // false for the centre tap (no -e partner)
+  float Kt[N + 1][N + 1];
+};
+
+template <int Q1, int N, bool SHOCK, int BY, int BZ>
+__device__ __forceinline__ void line_group_lane(const float* __restrict__ src, long long stride,
+                                                const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                                const LaneTap<N>& T, float (&a32)[n_moments(N)]) {
+  constexpr int NO = N - BY - BZ;
+  float acc[NO + 1];
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.f;
+#pragma unroll
+  for (int a = 0; a <= NO; ++a) {
+    const int field = midx(a, BY, BZ);
+    const float* __restrict__ row = src + static_cast<size_t>(field) * stride;
+    auto tap = [&](unsigned off, int g) {
+      float v = load_at(row, off);
+      if (SHOCK && any_ghost) {
+        const float gv = ghost_m[static_cast<size_t>(field) * n_ghost + (g < 0 ? 0 : g)];
+        v = g < 0 ? v : gv;
+      }
+      return v;
+    };
+    const float vp = tap(T.op, T.gp);
+    const float vm = T.pair ? tap(T.om, T.gm) : 0.f;
+    const float s = vp + vm, dd = vp - vm;
+#pragma unroll
+    for (int b = 0; b <= NO; ++b) acc[b] = fmaf(T.Kt[b][a], ((a + b) & 1) ? dd : s, acc[b]);
+  }
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) {
+    asm volatile("" : "+v"(acc[b]));
+    a32[midx(b, BY, BZ)] = acc[b];
+  }
+  if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
+}
+
+template <int Q1, int N, bool SHOCK, int BY, int BZ>
+__device__ __forceinline__ void line_groups_lane(const float* __restrict__ src, long long stride,
+                                                 const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                                 const LaneTap<N>& T, float (&a32)[n_moments(N)]) {
+  if constexpr (BY <= N) {
+    if constexpr (BY + BZ <= N) {
+      line_group_lane<Q1, N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+      line_groups_lane<Q1, N, SHOCK, BY, BZ + 1>(src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+    } else {
+      line_groups_lane<Q1, N, SHOCK, BY + 1, 0>(src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+    }
+  }
+}
+
+// One node of a line domain per LPN work-items; work-groups of 64 work-items cover 64 / LPN nodes
+// of the block table (any number of line domains, each of its own length and end states).
+// ghost_m: float32 [M][n_ghost] moments of the end states (columns 2 d, 2 d + 1 for domain d).
+template <int Q1, int N, bool SHOCK, int LPN = 1>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_line_collide(
+    LatticeConst L, MomentTaps32 K, StepArgs A, const float* __restrict__ ghost_m, const float* __restrict__ src,
+    float* __restrict__ dst) {
   using S = Taps1D<Q1>;
   constexpr int M = n_moments(N);
   const BlockDev bd = A.blocks[blockIdx.x];
   const DomainDev D = A.doms[bd.dom];
-  const int x = bd.first + static_cast<int>(threadIdx.x);
-  if (x >= D.nx) return;
+  const int x = bd.first + static_cast<int>(threadIdx.x) / LPN;
+  const int sub = static_cast<int>(threadIdx.x) % LPN;
+  if (x >= D.nx) return;                      // whole groups: the lanes of a node share x
   const int row0 = static_cast<int>(D.off);
-  LineTaps<Q1> T;
   bool ghost = false;
   auto source = [&](int xs, unsigned& off, int& g) {
     g = -1;
@@ -391,14 +473,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
     }
     off = static_cast<unsigned>(row0 + xs) * 4u;
   };
-#pragma unroll
-  for (int t = 0; t <= S::p; ++t) {
-    source(x - S::e[t] - L.k[0], T.op[t], T.gp[t]);
-    source(x + S::e[t] - L.k[0], T.om[t], T.gm[t]);
-  }
-  const bool any_ghost = SHOCK && __any(ghost);
   float a32[M];
-  line_groups<Q1, N, SHOCK, 0, 0>(K, src, A.stride, ghost_m, A.n_ghost, any_ghost, T, a32);
+  if constexpr (LPN == 1) {
+    LineTaps<Q1> T;
+#pragma unroll
+    for (int t = 0; t <= S::p; ++t) {
+      source(x - S::e[t] - L.k[0], T.op[t], T.gp[t]);
+      source(x + S::e[t] - L.k[0], T.om[t], T.gm[t]);
+    }
+    const bool any_ghost = SHOCK && __any(ghost);
+    line_groups<Q1, N, SHOCK, 0, 0>(K, src, A.stride, ghost_m, A.n_ghost, any_ghost, T, a32);
+  } else {
+    static_assert(LPN > S::p, "one tap pair per lane");
+    LaneTap<N> T;
+    const int t = sub <= S::p ? sub : 0;
+    int e = S::e[0];
+#pragma unroll
+    for (int j = 1; j <= S::p; ++j) e = t == j ? S::e[j] : e;
+#pragma unroll
+    for (int b = 0; b <= N; ++b)
+#pragma unroll
+      for (int a = 0; a <= N; ++a) {
+        float v = K.K[0][b][a];
+#pragma unroll
+        for (int j = 1; j <= S::p; ++j) v = t == j ? K.K[j][b][a] : v;
+        T.Kt[b][a] = sub <= S::p ? v : 0.f;     // lanes beyond the taps contribute nothing
+      }
+    T.pair = t > 0;
+    source(x - e - L.k[0], T.op, T.gp);
+    source(x + e - L.k[0], T.om, T.gm);
+    const bool any_ghost = SHOCK && __any(ghost);
+    line_groups_lane<Q1, N, SHOCK, 0, 0>(src, A.stride, ghost_m, A.n_ghost, any_ghost, T, a32);
+    group_allreduce_f32<LPN, M>(a32);
+  }
   double d[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
@@ -409,6 +516,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
   to_local<N>(d, mac);
   relax<N>(d, L, mac.rho, mac.tsc);
   to_lattice<N>(d, mac);
+  // with LPN > 1 every lane of the group stores the same values to the same addresses
   const unsigned off = static_cast<unsigned>(row0 + x) * 4u;
 #pragma unroll
   for (int i = 0; i < M; ++i) store_at(dst + static_cast<size_t>(i) * A.stride, off, static_cast<float>(d[i]));

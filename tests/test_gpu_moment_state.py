@@ -296,3 +296,21 @@ def test_line_batch_equals_separate_contexts(torch):
         one.sync()
         assert torch.equal(out[:, :nx], mb[:, off:off + nx]), i
         off += nx
+
+
+@pytest.mark.parametrize("stencil,N", [(D1Q7, 4), (D1Q9, 5)], ids=["q343_n4", "q729_n5"])
+def test_line_lanes_per_node_agree(torch, stencil, N):
+    """Eight lanes per node (one tap pair each, DPP group sums) against one lane per node: the
+    same step up to the order of the FP32 tap sums."""
+    lat, fields = _line_case(stencil, N, [(3.0, 150)])
+    n = lat.n_nodes
+    m0 = _noisy_moments(torch, lat, fields, seed=35)
+    outs = {}
+    for lanes in (1, 8):
+        lat.set_launch("direct", 0, 64, lanes)
+        outs[lanes] = lat.step_moment_state(m0.clone(), lat.new_moment_state(), lat.new_moment_work(), 4)
+        lat.sync()
+    a, b = outs[1][:, :n].double(), outs[8][:, :n].double()
+    err = float((a - b).abs().max() / a.abs().max())
+    print(f"line moment state, 8 lanes vs 1 lane per node after 4 steps: {err:.2e}")
+    assert err < 2e-6, err
