@@ -21,7 +21,27 @@ from .presets import tau_table
 from .shocks import shock_domain
 
 
+class MomentStepper:
+    """Adapter that advances a moment state (lbsmrt_step_moment_state) behind the step / moments
+    calls run_to_steady makes; moments are taken from the expanded populations."""
+
+    def __init__(self, lat):
+        self.lat = lat
+        self.work = lat.new_moment_work()
+        self.f = lat.new_state()
+
+    def step(self, ma, mb, n):
+        return self.lat.step_moment_state(ma, mb, self.work, n)
+
+    def moments(self, m, mask):
+        return self.lat.moments(self.lat.expand_state(m, out=self.f), mask)
+
+    def sync(self):
+        self.lat.sync()
+
+
 def run_to_steady(lat, fa, fb, every=100, max_steps=400000, tol_abs=1e-8, ulps=8, progress=None):
+    """lat: a Lattice (fa, fb population states) or a MomentStepper (fa, fb moment states)."""
     m = lat.moments(fa, C.MOM_BASIC)
     prev = torch.stack([m[0], m[4]]).cpu().numpy()
     steps = 0
@@ -68,6 +88,8 @@ def main():
                     help="lanes per node of the step kernel (0: the library's default)")
     ap.add_argument("--additive", action="store_true",
                     help="additive collision f* = g + R (a' - a) instead of the rebuild from the moments")
+    ap.add_argument("--moment-state", action="store_true",
+                    help="hold the state as the M moments of each node (lbsmrt_step_moment_state)")
     args = ap.parse_args()
     ab, deg = {"d1q7": ([1, 2, 3], 9), "d1q9": ([1, 2, 3, 5], 11),
                "d1q17": ([1, 2, 3, 4, 5, 6, 7, 9], 19)}[args.stencil]
@@ -80,18 +102,24 @@ def main():
                   precision="fp64_contract", regularized=not args.additive)
     if args.lanes_per_node:
         lat.set_launch("direct", 0, 64, args.lanes_per_node)
-    fa = lat.equilibrium(torch.tensor(fields, dtype=torch.float64, device="cuda"))
-    fb = lat.new_state()
+    fields_t = torch.tensor(fields, dtype=torch.float64, device="cuda")
+    if args.moment_state:
+        stepper = MomentStepper(lat)
+        fa, fb = lat.equilibrium_moments(fields_t), lat.new_moment_state()
+    else:
+        stepper = lat
+        fa, fb = lat.equilibrium(fields_t), lat.new_state()
     t0 = time.time()
-    res, fa = run_to_steady(lat, fa, fb, max_steps=args.max_steps,
+    res, fa = run_to_steady(stepper, fa, fb, max_steps=args.max_steps,
                             progress=lambda s: print(s, file=sys.stderr, flush=True))
     res["wall_s"] = round(time.time() - t0, 2)
     if res.get("converged"):
-        m = lat.moments(fa, C.MOM_BASIC | C.MOM_Q).cpu().numpy()
+        m = stepper.moments(fa, C.MOM_BASIC | C.MOM_Q).cpu().numpy()
         res["shock_thickness_cells"] = round(shock_thickness(m[0], st), 3)
         res["max_theta"] = round(float(m[4].max()), 4)
         res["min_q_x"] = round(float(m[5].min()), 6)
     res.update(mach=args.mach, nx=args.nx, tau=args.tau, Q=lat.Q, N=lat.N, k=k, additive=args.additive,
+               moment_state=args.moment_state,
                theta1=st["theta1"],
                theta2=st["theta2"], rho2=st["rho2"], launch=lat.launch_settings())
     print(json.dumps(res), flush=True)
