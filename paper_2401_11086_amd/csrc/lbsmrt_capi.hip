@@ -250,16 +250,16 @@ struct Launch {
       A.blocks = split ? c->d_blocks_adj8 : c->d_blocks_adj;
       const int nb = split ? c->n_blocks_adj8 : c->n_blocks_adj;
       if (split && c->shock)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
                            c->d_ghost_m, src, dst);
       else if (split)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
                            c->d_ghost_m, src, dst);
       else if (c->shock)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
                            c->d_ghost_m, src, dst);
       else
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, c->ms_k32, A,
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
                            c->d_ghost_m, src, dst);
     }
   }

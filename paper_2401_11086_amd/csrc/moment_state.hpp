@@ -297,6 +297,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
 // for a, b <= N (the quadrature is exact to degree 2N), so passes z and y are the identity and
 // the step is the x-stage on the moment fields themselves, followed by the collision.  Pulls
 // from beyond a shock tube's ends read the moments of its fixed end states.
+//
+// The x-stage runs in FP64 and factored through the populations: for each tap pair +-e_t the
+// rebuilt populations F(+-e_t) = sum_a Rw_a(c_t) m_a(x -+ e_t) (eq:fi) are formed, folded by
+// parity, and projected with He_b(c_t) (eq:an).  With FP64 tables the quadrature identity holds
+// to FP64 rounding, so a tube conserves mass, momentum and energy up to the float32 storage of
+// the moments (FP32 taps drift a steady shock by ~1e-6 of the mass per step).
 
 // Sources of the x taps of one node: byte offset into a moment row, or a ghost column.
 template <int Q1>
@@ -305,128 +311,112 @@ struct LineTaps {
   int gp[Taps1D<Q1>::p + 1], gm[Taps1D<Q1>::p + 1];         // -1 inside, else the ghost column
 };
 
-template <int Q1, int N, bool SHOCK, int BY, int BZ>
-__device__ __forceinline__ void line_group(const MomentTaps32& K, const float* __restrict__ src, long long stride,
-                                           const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
-                                           const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
-  using S = Taps1D<Q1>;
+// Moment field a of group (BY, BZ) at one tap source (ghost value past a tube's end).
+template <bool SHOCK>
+__device__ __forceinline__ double line_tap(const float* __restrict__ row, unsigned off, int g,
+                                           const float* __restrict__ ghost_col, bool any_ghost) {
+  float v = load_at(row, off);
+  if (SHOCK && any_ghost) {
+    const float gv = ghost_col[g < 0 ? 0 : g];
+    v = g < 0 ? v : gv;
+  }
+  return static_cast<double>(v);
+}
+
+// One tap pair's contribution to group (BY, BZ): he[b] = He_b(c_t), rw[a] = Rw_a(c_t) (FP64),
+// pair false for the centre tap.
+template <int N, bool SHOCK, int BY, int BZ>
+__device__ __forceinline__ void line_tap_pair(const float* __restrict__ src, long long stride,
+                                              const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                              unsigned op, int gp, unsigned om, int gm, bool pair,
+                                              const double (&he)[N + 1], const double (&rw)[N + 1], double* acc) {
   constexpr int NO = N - BY - BZ;
-  float acc[NO + 1];
-#pragma unroll
-  for (int b = 0; b <= NO; ++b) acc[b] = 0.f;
+  double ev = 0.0, od = 0.0;   // rebuilt population folded: even part (for even b), odd part
 #pragma unroll
   for (int a = 0; a <= NO; ++a) {
     const int field = midx(a, BY, BZ);
     const float* __restrict__ row = src + static_cast<size_t>(field) * stride;
-    auto tap = [&](unsigned off, int g) {
-      float v = load_at(row, off);
-      if (SHOCK && any_ghost) {
-        const float gv = ghost_m[static_cast<size_t>(field) * n_ghost + (g < 0 ? 0 : g)];
-        v = g < 0 ? v : gv;
-      }
-      return v;
-    };
-    if (!(a & 1)) {
-      const float c = tap(T.op[0], T.gp[0]);
-#pragma unroll
-      for (int b = 0; b <= NO; b += 2) acc[b] = fmaf(K.K[0][b][a], c, acc[b]);
-    }
-#pragma unroll
-    for (int t = 1; t <= S::p; ++t) {
-      const float vp = tap(T.op[t], T.gp[t]);
-      const float vm = tap(T.om[t], T.gm[t]);
-      const float s = vp + vm, dd = vp - vm;
-#pragma unroll
-      for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
-    }
+    const float* __restrict__ gcol = ghost_m + static_cast<size_t>(field) * n_ghost;
+    const double vp = line_tap<SHOCK>(row, op, gp, gcol, any_ghost);
+    const double vm = pair ? line_tap<SHOCK>(row, om, gm, gcol, any_ghost) : 0.0;
+    const double s = vp + vm, dd = vp - vm;
+    // K_{ba} uses s when a + b is even, d when odd
+    ev = fma(rw[a], (a & 1) ? dd : s, ev);
+    od = fma(rw[a], (a & 1) ? s : dd, od);
   }
-  // as in pass x: pin the sums, and fence the loads after every kGroupsPerPhase groups
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = fma(he[b], (b & 1) ? od : ev, acc[b]);
+}
+
+template <int Q1, int N, bool SHOCK, int BY, int BZ>
+__device__ __forceinline__ void line_group(const LatticeConst& L, const float* __restrict__ src, long long stride,
+                                           const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                           const LineTaps<Q1>& T, double (&d)[n_moments(N)]) {
+  using S = Taps1D<Q1>;
+  constexpr int NO = N - BY - BZ;
+  constexpr int p = Q1 / 2;
+  double acc[NO + 1];
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
+#pragma unroll
+  for (int t = 0; t <= S::p; ++t) {
+    double he[N + 1], rw[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) {
+      he[n] = L.He64[p + t][n];
+      rw[n] = L.Rw64[p + t][n];
+    }
+    line_tap_pair<N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T.op[t], T.gp[t], T.om[t], T.gm[t],
+                                    t > 0, he, rw, acc);
+  }
+  // pin the sums, and fence the loads after every kGroupsPerPhase groups (as in pass x)
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
     asm volatile("" : "+v"(acc[b]));
-    a32[midx(b, BY, BZ)] = acc[b];
+    d[midx(b, BY, BZ)] = acc[b];
   }
   if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
-__device__ __forceinline__ void line_groups(const MomentTaps32& K, const float* __restrict__ src, long long stride,
+__device__ __forceinline__ void line_groups(const LatticeConst& L, const float* __restrict__ src, long long stride,
                                             const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
-                                            const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
+                                            const LineTaps<Q1>& T, double (&d)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      line_group<Q1, N, SHOCK, BY, BZ>(K, src, stride, ghost_m, n_ghost, any_ghost, T, a32);
-      line_groups<Q1, N, SHOCK, BY, BZ + 1>(K, src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+      line_group<Q1, N, SHOCK, BY, BZ>(L, src, stride, ghost_m, n_ghost, any_ghost, T, d);
+      line_groups<Q1, N, SHOCK, BY, BZ + 1>(L, src, stride, ghost_m, n_ghost, any_ghost, T, d);
     } else {
-      line_groups<Q1, N, SHOCK, BY + 1, 0>(K, src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+      line_groups<Q1, N, SHOCK, BY + 1, 0>(L, src, stride, ghost_m, n_ghost, any_ghost, T, d);
     }
   }
 }
 
-// Lanes per node in the line kernel: lane `sub` of a node's group takes the tap pair e_sub of the
-// x-stage (the centre for sub = 0, nothing for sub > p) for every group, and the group sums the
-// partial moments with DPP moves inside each row (as the population kernel does), so every
-// lane holds the same sums and runs the same collision.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move_f32(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-
-template <int LPN, int M>
-__device__ __forceinline__ void group_allreduce_f32(float (&a)[M]) {
-  static_assert(LPN == 4 || LPN == 8, "groups of 4 or 8 lanes");
-  constexpr int kSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
-  constexpr int kSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
-  constexpr int kHalfMirror = 0x141;                            // row_half_mirror
-#pragma unroll
-  for (int i = 0; i < M; ++i) a[i] += dpp_move_f32<kSwap1>(a[i]);
-#pragma unroll
-  for (int i = 0; i < M; ++i) a[i] += dpp_move_f32<kSwap2>(a[i]);
-  if constexpr (LPN == 8) {
-#pragma unroll
-    for (int i = 0; i < M; ++i) a[i] += dpp_move_f32<kHalfMirror>(a[i]);
-  }
-}
-
-// One lane's tap pair: sources of +e and -e (or the centre), and its 1D table K[t][b][a].
+// Lanes per node: lane `sub` of a node's group takes the tap pair e_sub (the centre for sub = 0,
+// nothing for sub > p) for every group, and the group sums the partial moments with the DPP row
+// moves of the population kernel, so every lane holds the same sums and runs the same collision.
 template <int N>
 struct LaneTap {
   unsigned op, om;
   int gp, gm;
   bool pair;                          // false for the centre tap (no -e partner)
-  float Kt[N + 1][N + 1];
+  double he[N + 1], rw[N + 1];        // He_b(c_t), Rw_a(c_t) of the lane's tap (zero beyond the taps)
 };
 
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
 __device__ __forceinline__ void line_group_lane(const float* __restrict__ src, long long stride,
                                                 const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
-                                                const LaneTap<N>& T, float (&a32)[n_moments(N)]) {
+                                                const LaneTap<N>& T, double (&d)[n_moments(N)]) {
   constexpr int NO = N - BY - BZ;
-  float acc[NO + 1];
+  double acc[NO + 1];
 #pragma unroll
-  for (int b = 0; b <= NO; ++b) acc[b] = 0.f;
-#pragma unroll
-  for (int a = 0; a <= NO; ++a) {
-    const int field = midx(a, BY, BZ);
-    const float* __restrict__ row = src + static_cast<size_t>(field) * stride;
-    auto tap = [&](unsigned off, int g) {
-      float v = load_at(row, off);
-      if (SHOCK && any_ghost) {
-        const float gv = ghost_m[static_cast<size_t>(field) * n_ghost + (g < 0 ? 0 : g)];
-        v = g < 0 ? v : gv;
-      }
-      return v;
-    };
-    const float vp = tap(T.op, T.gp);
-    const float vm = T.pair ? tap(T.om, T.gm) : 0.f;
-    const float s = vp + vm, dd = vp - vm;
-#pragma unroll
-    for (int b = 0; b <= NO; ++b) acc[b] = fmaf(T.Kt[b][a], ((a + b) & 1) ? dd : s, acc[b]);
-  }
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
+  line_tap_pair<N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T.op, T.gp, T.om, T.gm, T.pair, T.he,
+                                  T.rw, acc);
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
     asm volatile("" : "+v"(acc[b]));
-    a32[midx(b, BY, BZ)] = acc[b];
+    d[midx(b, BY, BZ)] = acc[b];
   }
   if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
@@ -434,13 +424,13 @@ __device__ __forceinline__ void line_group_lane(const float* __restrict__ src, l
 template <int Q1, int N, bool SHOCK, int BY, int BZ>
 __device__ __forceinline__ void line_groups_lane(const float* __restrict__ src, long long stride,
                                                  const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
-                                                 const LaneTap<N>& T, float (&a32)[n_moments(N)]) {
+                                                 const LaneTap<N>& T, double (&d)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      line_group_lane<Q1, N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T, a32);
-      line_groups_lane<Q1, N, SHOCK, BY, BZ + 1>(src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+      line_group_lane<Q1, N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T, d);
+      line_groups_lane<Q1, N, SHOCK, BY, BZ + 1>(src, stride, ghost_m, n_ghost, any_ghost, T, d);
     } else {
-      line_groups_lane<Q1, N, SHOCK, BY + 1, 0>(src, stride, ghost_m, n_ghost, any_ghost, T, a32);
+      line_groups_lane<Q1, N, SHOCK, BY + 1, 0>(src, stride, ghost_m, n_ghost, any_ghost, T, d);
     }
   }
 }
@@ -450,10 +440,11 @@ __device__ __forceinline__ void line_groups_lane(const float* __restrict__ src, 
 // ghost_m: float32 [M][n_ghost] moments of the end states (columns 2 d, 2 d + 1 for domain d).
 template <int Q1, int N, bool SHOCK, int LPN = 1>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_line_collide(
-    LatticeConst L, MomentTaps32 K, StepArgs A, const float* __restrict__ ghost_m, const float* __restrict__ src,
+    LatticeConst L, StepArgs A, const float* __restrict__ ghost_m, const float* __restrict__ src,
     float* __restrict__ dst) {
   using S = Taps1D<Q1>;
   constexpr int M = n_moments(N);
+  constexpr int p = Q1 / 2;
   const BlockDev bd = A.blocks[blockIdx.x];
   const DomainDev D = A.doms[bd.dom];
   const int x = bd.first + static_cast<int>(threadIdx.x) / LPN;
@@ -473,7 +464,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
     }
     off = static_cast<unsigned>(row0 + xs) * 4u;
   };
-  float a32[M];
+  double d[M];
   if constexpr (LPN == 1) {
     LineTaps<Q1> T;
 #pragma unroll
@@ -482,7 +473,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
       source(x + S::e[t] - L.k[0], T.om[t], T.gm[t]);
     }
     const bool any_ghost = SHOCK && __any(ghost);
-    line_groups<Q1, N, SHOCK, 0, 0>(K, src, A.stride, ghost_m, A.n_ghost, any_ghost, T, a32);
+    line_groups<Q1, N, SHOCK, 0, 0>(L, src, A.stride, ghost_m, A.n_ghost, any_ghost, T, d);
   } else {
     static_assert(LPN > S::p, "one tap pair per lane");
     LaneTap<N> T;
@@ -491,24 +482,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
 #pragma unroll
     for (int j = 1; j <= S::p; ++j) e = t == j ? S::e[j] : e;
 #pragma unroll
-    for (int b = 0; b <= N; ++b)
+    for (int n = 0; n <= N; ++n) {
+      double h = L.He64[p][n], r = L.Rw64[p][n];
 #pragma unroll
-      for (int a = 0; a <= N; ++a) {
-        float v = K.K[0][b][a];
-#pragma unroll
-        for (int j = 1; j <= S::p; ++j) v = t == j ? K.K[j][b][a] : v;
-        T.Kt[b][a] = sub <= S::p ? v : 0.f;     // lanes beyond the taps contribute nothing
+      for (int j = 1; j <= S::p; ++j) {
+        h = t == j ? L.He64[p + j][n] : h;
+        r = t == j ? L.Rw64[p + j][n] : r;
       }
+      T.he[n] = sub <= S::p ? h : 0.0;          // lanes beyond the taps contribute nothing
+      T.rw[n] = r;
+    }
     T.pair = t > 0;
     source(x - e - L.k[0], T.op, T.gp);
     source(x + e - L.k[0], T.om, T.gm);
     const bool any_ghost = SHOCK && __any(ghost);
-    line_groups_lane<Q1, N, SHOCK, 0, 0>(src, A.stride, ghost_m, A.n_ghost, any_ghost, T, a32);
-    group_allreduce_f32<LPN, M>(a32);
+    line_groups_lane<Q1, N, SHOCK, 0, 0>(src, A.stride, ghost_m, A.n_ghost, any_ghost, T, d);
+    group_allreduce<LPN, M>(d);
   }
-  double d[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
   double S5[5];
   sums_from_a<N>(d, L, S5);
   Macro mac = macro_from_sums(L, S5, A.err);
