@@ -61,7 +61,7 @@ struct lbsmrt_ctx {
   bool ms_ok = false;
   bool ms_lines = false;
   float* d_ghost_m = nullptr;        // [M][n_ghost] moments of the end states (line domains)
-  MomentTaps32 ms_k32{};
+  MomentTables64 ms_tab{};          // 1D tables of the non-negative taps
 };
 
 namespace {
@@ -232,11 +232,11 @@ struct Launch {
       const long long lz = static_cast<long long>(G.nx) * G.ny, ly = static_cast<long long>(G.nx) * G.nz;
       const int Tz = ms_chunk(lz, G.nz), Ty = ms_chunk(ly, G.ny);
       hipLaunchKernelGGL((k_ms_pass_z<Q1, N>), dim3(static_cast<unsigned>((lz + 255) / 256), (G.nz + Tz - 1) / Tz),
-                         dim3(256), 0, s, c->ms_k32, G, src, t1, Tz);
+                         dim3(256), 0, s, c->ms_tab, G, src, t1, Tz);
       hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
-                         dim3(256), 0, s, c->ms_k32, G, t1, t2, Ty);
+                         dim3(256), 0, s, c->ms_tab, G, t1, t2, Ty);
       hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
-                         c->ms_k32, G, t2, dst);
+                         G, t2, dst);
     }
   }
   // Line domains: eight lanes per node (one tap pair each) when the context splits nodes over
@@ -539,18 +539,18 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   const size_t partial_rows =
       static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8, c->n_blocks_adjR}));
   c->n_ghost = 2 * n_domains;
-  // moment-state form (lbsmrt_step_moment_state): K[t][b][a] = He_b(c_t) w_t He_a(c_t)/a! at the
-  // non-negative taps t of the stencil
+  // moment-state form (lbsmrt_step_moment_state): the FP64 1D tables of the non-negative taps t,
+  // K_{b a}(e_t) = He_b(c_t) Rw_a(c_t)
   dispatch(c->Q1, c->N, [&](auto l) { c->ms_ok = decltype(l)::ms_taps_match(c); });
   bool lines = true;
   for (int i = 0; i < n_domains; ++i) lines = lines && domains[i].ny == 1 && domains[i].nz == 1;
   c->ms_lines = c->ms_ok && lines && !c->additive;
   c->ms_ok = c->ms_ok && !c->additive && (lines || (n_domains == 1 && domains[0].bc_x == 0));
   for (int t = 0; t <= p && t < kMsMaxTaps; ++t)
-    for (int b = 0; b <= c->N; ++b)
-      for (int a = 0; a <= c->N; ++a) {
-        c->ms_k32.K[t][b][a] = static_cast<float>(L.He64[p + t][b] * L.Rw64[p + t][a]);
-      }
+    for (int n = 0; n <= c->N; ++n) {
+      c->ms_tab.He[t][n] = L.He64[p + t][n];
+      c->ms_tab.Rw[t][n] = L.Rw64[p + t][n];
+    }
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return LBSMRT_E_HIP; }

@@ -15,9 +15,12 @@
 //
 // Passes z and y march each work-item along its line with a register ring of the last W rows
 // (W = 2 max|e| + 1), so every input row is read once per line chunk of T rows (T a multiple of
-// W, chosen by the host so that the launch has enough waves); the taps are
-// folded over +-e (K(-e) = (-1)^(a+b) K(e)).  Pass x reads its row's shifted neighbours directly
-// (same cache lines as the row itself); the collision runs in FP64.
+// W, chosen by the host so that the launch has enough waves).  Pass x reads its row's shifted
+// neighbours directly (same cache lines as the row itself).  Every pass applies a tap pair +-e_t
+// factored through the populations: the rebuilt values F(+-e_t) = sum_a Rw_a(c_t) v_a are
+// folded by parity (K(-e) = (-1)^(a+b) K(e)) and projected with He_b(c_t), in FP64 with FP64
+// tables, so the quadrature identity sum_e K_{b a}(e) = delta_ab, and with it the conservation
+// of mass, momentum and energy, holds up to the float32 storage of the fields.
 #pragma once
 #include "kernels.hpp"
 
@@ -40,17 +43,18 @@ struct Taps1D<9> {
   static constexpr int e[5] = {0, 1, 2, 3, 5};
 };
 template <>
-struct Taps1D<17> {   // D1Q17: no moment-state kernel (more taps than MomentTaps32 holds)
+struct Taps1D<17> {   // D1Q17: no moment-state kernel (more taps than MomentTables64 holds)
   static constexpr int p = 8;
   static constexpr int H = 9;
   static constexpr int e[9] = {0, 1, 2, 3, 4, 5, 6, 7, 9};
 };
 
-// K[t][b][a] = He_b(c) w He_a(c) / a! at the non-negative tap t (c = r e_t); stencils of up to
-// nine points have a moment-state kernel.
+// 1D tables of the non-negative taps t (c = r e_t): He[t][b] = He_b(c), Rw[t][a] = w He_a(c) / a!,
+// so K_{b a}(e_t) = He[t][b] Rw[t][a].  Stencils of up to nine points have a moment-state kernel.
 constexpr int kMsMaxTaps = 5;
-struct MomentTaps32 {
-  float K[kMsMaxTaps][kMaxN + 1][kMaxN + 1];
+struct MomentTables64 {
+  double He[kMsMaxTaps][kMaxN + 1];
+  double Rw[kMsMaxTaps][kMaxN + 1];
 };
 
 struct MsGeom {
@@ -65,7 +69,7 @@ struct MsGeom {
 // has byte offset base + q * step.  Inputs: fields fin[a], a < nf (the 1D index a of the
 // convolved axis); outputs: fields fout[b], b < no (1D index b).
 template <int Q1, int N>
-__device__ __forceinline__ void march_line(const MomentTaps32& K, const float* __restrict__ in,
+__device__ __forceinline__ void march_line(const MomentTables64& K, const float* __restrict__ in,
                                            float* __restrict__ out, long long stride, const int (&fin)[N + 1],
                                            int nf, const int (&fout)[N + 1], int no, unsigned base, unsigned step,
                                            int len, int p0, int T, int kshift) {
@@ -100,31 +104,39 @@ __device__ __forceinline__ void march_line(const MomentTaps32& K, const float* _
       }
       const int pos = p0 + jb + jj;
       if (pos < len) {
-        float acc[N + 1];
+        double acc[N + 1];
 #pragma unroll
-        for (int b = 0; b <= N; ++b) acc[b] = 0.f;
+        for (int b = 0; b <= N; ++b) acc[b] = 0.0;
+        // centre tap (He and Rw vanish at c = 0 for odd orders): the tap e pulls line position
+        // pos - e - kshift = ring slot (jj + H - e) % W
+        {
+          double c = 0.0;
 #pragma unroll
-        for (int a = 0; a <= N; ++a) {
-          if (a >= nf) continue;
-          // the tap e pulls line position pos - e - kshift = ring slot (jj + H - e) % W
-          if (!(a & 1)) {
-            const float c = ring[(jj + H) % W][a];
+          for (int a = 0; a <= N; a += 2)
+            if (a < nf) c = fma(K.Rw[0][a], static_cast<double>(ring[(jj + H) % W][a]), c);
 #pragma unroll
-            for (int b = 0; b <= N; b += 2) acc[b] = fmaf(K.K[0][b][a], c, acc[b]);
-          }
+          for (int b = 0; b <= N; b += 2) acc[b] = fma(K.He[0][b], c, acc[b]);
+        }
 #pragma unroll
-          for (int t = 1; t <= S::p; ++t) {
+        for (int t = 1; t <= S::p; ++t) {
+          double ev = 0.0, od = 0.0;
+#pragma unroll
+          for (int a = 0; a <= N; ++a) {
+            if (a >= nf) continue;
+            // the fold is rounded in FP32 (unbiased); the tables and the sums stay FP64
             const float vp = ring[(jj + H - S::e[t]) % W][a];
             const float vm = ring[(jj + H + S::e[t]) % W][a];
-            const float s = vp + vm, d = vp - vm;
-#pragma unroll
-            for (int b = 0; b <= N; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? d : s, acc[b]);
+            const double sm = static_cast<double>(vp + vm), df = static_cast<double>(vp - vm);
+            ev = fma(K.Rw[t][a], (a & 1) ? df : sm, ev);
+            od = fma(K.Rw[t][a], (a & 1) ? sm : df, od);
           }
+#pragma unroll
+          for (int b = 0; b <= N; ++b) acc[b] = fma(K.He[t][b], (b & 1) ? od : ev, acc[b]);
         }
         const unsigned off = base + static_cast<unsigned>(pos) * step;
 #pragma unroll
         for (int b = 0; b <= N; ++b)
-          if (b < no) store_at(out + static_cast<size_t>(fout[b]) * stride, off, acc[b]);
+          if (b < no) store_at(out + static_cast<size_t>(fout[b]) * stride, off, static_cast<float>(acc[b]));
       }
     }
   }
@@ -134,7 +146,7 @@ __device__ __forceinline__ void march_line(const MomentTaps32& K, const float* _
 // lines numbered x fastest over the plane (so a wave reads contiguous 256 B); grid
 // (ceil(nx ny / 256), ceil(nz / T)), each work-item marching T rows.
 template <int Q1, int N>
-__global__ __launch_bounds__(256) void k_ms_pass_z(MomentTaps32 K, MsGeom G, const float* __restrict__ m,
+__global__ __launch_bounds__(256) void k_ms_pass_z(MomentTables64 K, MsGeom G, const float* __restrict__ m,
                                                    float* __restrict__ t1, int T) {
   const int line = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
   if (line >= G.nx * G.ny) return;
@@ -157,7 +169,7 @@ __global__ __launch_bounds__(256) void k_ms_pass_z(MomentTaps32 K, MsGeom G, con
 // Pass y: t1[pair(ax, ay) (N+1) + bz] -> t2[ax P2 + pair(by, bz)].  One work-item per y line
 // (x, z), x fastest; grid (ceil(nx nz / 256), ceil(ny / T)).
 template <int Q1, int N>
-__global__ __launch_bounds__(256) void k_ms_pass_y(MomentTaps32 K, MsGeom G, const float* __restrict__ t1,
+__global__ __launch_bounds__(256) void k_ms_pass_y(MomentTables64 K, MsGeom G, const float* __restrict__ t1,
                                                    float* __restrict__ t2, int T) {
   constexpr int P2 = n_sym(N);
   const int line = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
@@ -195,33 +207,41 @@ constexpr int group_index(int N, int BY, int BZ) {
 constexpr int kGroupsPerPhase = LBSMRT_GROUPS_PER_PHASE;
 
 // One (by, bz) group of pass x: a[bx, by, bz] = sum_ax sum_e K_{bx ax}(e) t2[ax, by, bz](x - e - k_x)
-// for bx <= N - by - bz (FP32 sums, taps folded over +-e).
+// for bx <= N - by - bz, in FP64, each tap pair factored through the rebuilt populations.
 template <int Q1, int N, int BY, int BZ>
-__device__ __forceinline__ void x_group(const MomentTaps32& K, const float* __restrict__ t2, long long stride,
+__device__ __forceinline__ void x_group(const LatticeConst& L, const float* __restrict__ t2, long long stride,
                                         const unsigned (&op)[Taps1D<Q1>::p + 1],
-                                        const unsigned (&om)[Taps1D<Q1>::p + 1], float (&a32)[n_moments(N)]) {
+                                        const unsigned (&om)[Taps1D<Q1>::p + 1], double (&d)[n_moments(N)]) {
   using S = Taps1D<Q1>;
   constexpr int P2 = n_sym(N);
   constexpr int NO = N - BY - BZ;
-  float acc[NO + 1];
+  constexpr int p = Q1 / 2;
+  const float* __restrict__ src[N + 1];
 #pragma unroll
-  for (int b = 0; b <= NO; ++b) acc[b] = 0.f;
+  for (int a = 0; a <= N; ++a) src[a] = t2 + static_cast<size_t>(a * P2 + pair_pos(BY, BZ)) * stride;
+  double acc[NO + 1];
 #pragma unroll
-  for (int a = 0; a <= N; ++a) {
-    const float* __restrict__ src = t2 + static_cast<size_t>(a * P2 + pair_pos(BY, BZ)) * stride;
-    if (!(a & 1)) {
-      const float c = load_at(src, op[0]);
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
+  {
+    double c = 0.0;                           // centre tap: even orders only
 #pragma unroll
-      for (int b = 0; b <= NO; b += 2) acc[b] = fmaf(K.K[0][b][a], c, acc[b]);
+    for (int a = 0; a <= N; a += 2) c = fma(L.Rw64[p][a], static_cast<double>(load_at(src[a], op[0])), c);
+#pragma unroll
+    for (int b = 0; b <= NO; b += 2) acc[b] = fma(L.He64[p][b], c, acc[b]);
+  }
+#pragma unroll
+  for (int t = 1; t <= S::p; ++t) {
+    double ev = 0.0, od = 0.0;
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+      const double vp = load_at(src[a], op[t]);
+      const double vm = load_at(src[a], om[t]);
+      const double sm = vp + vm, df = vp - vm;
+      ev = fma(L.Rw64[p + t][a], (a & 1) ? df : sm, ev);
+      od = fma(L.Rw64[p + t][a], (a & 1) ? sm : df, od);
     }
 #pragma unroll
-    for (int t = 1; t <= S::p; ++t) {
-      const float vp = load_at(src, op[t]);
-      const float vm = load_at(src, om[t]);
-      const float s = vp + vm, dd = vp - vm;
-#pragma unroll
-      for (int b = 0; b <= NO; ++b) acc[b] = fmaf(K.K[t][b][a], ((a + b) & 1) ? dd : s, acc[b]);
-    }
+    for (int b = 0; b <= NO; ++b) acc[b] = fma(L.He64[p + t][b], (b & 1) ? od : ev, acc[b]);
   }
   // Finish each group before later loads: the empty asm statements pin the sums here and fence
   // the loads every kGroupsPerPhase groups, otherwise every loaded value stays live until the
@@ -229,33 +249,31 @@ __device__ __forceinline__ void x_group(const MomentTaps32& K, const float* __re
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
     asm volatile("" : "+v"(acc[b]));
-    a32[midx(b, BY, BZ)] = acc[b];
+    d[midx(b, BY, BZ)] = acc[b];
   }
   if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
 // All groups (by, bz), by + bz <= N, in compile-time order.
 template <int Q1, int N, int BY, int BZ>
-__device__ __forceinline__ void x_groups(const MomentTaps32& K, const float* __restrict__ t2, long long stride,
+__device__ __forceinline__ void x_groups(const LatticeConst& L, const float* __restrict__ t2, long long stride,
                                          const unsigned (&op)[Taps1D<Q1>::p + 1],
-                                         const unsigned (&om)[Taps1D<Q1>::p + 1], float (&a32)[n_moments(N)]) {
+                                         const unsigned (&om)[Taps1D<Q1>::p + 1], double (&d)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      x_group<Q1, N, BY, BZ>(K, t2, stride, op, om, a32);
-      x_groups<Q1, N, BY, BZ + 1>(K, t2, stride, op, om, a32);
+      x_group<Q1, N, BY, BZ>(L, t2, stride, op, om, d);
+      x_groups<Q1, N, BY, BZ + 1>(L, t2, stride, op, om, d);
     } else {
-      x_groups<Q1, N, BY + 1, 0>(K, t2, stride, op, om, a32);
+      x_groups<Q1, N, BY + 1, 0>(L, t2, stride, op, om, d);
     }
   }
 }
 
 // Pass x + collision: t2[ax P2 + pair(by, bz)] -> a[bx, by, bz], SMRT collision (FP64), store a'.
-// The x-stage sums run in FP32 like the other two passes (the loads are FP32, and FP32 and FP64
-// FMAs issue at the same rate here, so converting every tap would only add work).
 // Grid (ceil(nx/256), ny, nz).
 template <int Q1, int N>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_pass_x_collide(LatticeConst L, MomentTaps32 K, MsGeom G,
-                                                           const float* __restrict__ t2, float* __restrict__ m_out) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_pass_x_collide(
+    LatticeConst L, MsGeom G, const float* __restrict__ t2, float* __restrict__ m_out) {
   using S = Taps1D<Q1>;
   constexpr int M = n_moments(N);
   const int x = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
@@ -274,11 +292,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
     op[t] = static_cast<unsigned>(row + sp) * 4u;
     om[t] = static_cast<unsigned>(row + sm) * 4u;
   }
-  float a32[M];
-  x_groups<Q1, N, 0, 0>(K, t2, G.stride, op, om, a32);
   double d[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
+  x_groups<Q1, N, 0, 0>(L, t2, G.stride, op, om, d);
   double S5[5];
   sums_from_a<N>(d, L, S5);
   Macro mac = macro_from_sums(L, S5, G.err);
