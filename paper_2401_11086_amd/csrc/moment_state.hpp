@@ -211,7 +211,7 @@ constexpr int kGroupsPerPhase = LBSMRT_GROUPS_PER_PHASE;
 template <int Q1, int N, int BY, int BZ>
 __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __restrict__ t2, long long stride,
                                         const unsigned (&op)[Taps1D<Q1>::p + 1],
-                                        const unsigned (&om)[Taps1D<Q1>::p + 1], double (&d)[n_moments(N)]) {
+                                        const unsigned (&om)[Taps1D<Q1>::p + 1], float (&a32)[n_moments(N)]) {
   using S = Taps1D<Q1>;
   constexpr int P2 = n_sym(N);
   constexpr int NO = N - BY - BZ;
@@ -234,9 +234,10 @@ __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __re
     double ev = 0.0, od = 0.0;
 #pragma unroll
     for (int a = 0; a <= N; ++a) {
-      const double vp = load_at(src[a], op[t]);
-      const double vm = load_at(src[a], om[t]);
-      const double sm = vp + vm, df = vp - vm;
+      // fold in FP32 (unbiased rounding) so the loads in flight stay one register each
+      const float vp = load_at(src[a], op[t]);
+      const float vm = load_at(src[a], om[t]);
+      const double sm = static_cast<double>(vp + vm), df = static_cast<double>(vp - vm);
       ev = fma(L.Rw64[p + t][a], (a & 1) ? df : sm, ev);
       od = fma(L.Rw64[p + t][a], (a & 1) ? sm : df, od);
     }
@@ -245,11 +246,14 @@ __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __re
   }
   // Finish each group before later loads: the empty asm statements pin the sums here and fence
   // the loads every kGroupsPerPhase groups, otherwise every loaded value stays live until the
-  // collision.
+  // collision.  The moments wait for the collision as float32 (the collision returns the
+  // conserved ones unchanged, and the store rounds them to float32 in any case), which keeps
+  // enough registers free for the loads of a group to be in flight together.
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
-    asm volatile("" : "+v"(acc[b]));
-    d[midx(b, BY, BZ)] = acc[b];
+    float v = static_cast<float>(acc[b]);
+    asm volatile("" : "+v"(v));
+    a32[midx(b, BY, BZ)] = v;
   }
   if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
@@ -258,13 +262,13 @@ __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __re
 template <int Q1, int N, int BY, int BZ>
 __device__ __forceinline__ void x_groups(const LatticeConst& L, const float* __restrict__ t2, long long stride,
                                          const unsigned (&op)[Taps1D<Q1>::p + 1],
-                                         const unsigned (&om)[Taps1D<Q1>::p + 1], double (&d)[n_moments(N)]) {
+                                         const unsigned (&om)[Taps1D<Q1>::p + 1], float (&a32)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      x_group<Q1, N, BY, BZ>(L, t2, stride, op, om, d);
-      x_groups<Q1, N, BY, BZ + 1>(L, t2, stride, op, om, d);
+      x_group<Q1, N, BY, BZ>(L, t2, stride, op, om, a32);
+      x_groups<Q1, N, BY, BZ + 1>(L, t2, stride, op, om, a32);
     } else {
-      x_groups<Q1, N, BY + 1, 0>(L, t2, stride, op, om, d);
+      x_groups<Q1, N, BY + 1, 0>(L, t2, stride, op, om, a32);
     }
   }
 }
@@ -292,8 +296,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
     op[t] = static_cast<unsigned>(row + sp) * 4u;
     om[t] = static_cast<unsigned>(row + sm) * 4u;
   }
+  float a32[M];
+  x_groups<Q1, N, 0, 0>(L, t2, G.stride, op, om, a32);
   double d[M];
-  x_groups<Q1, N, 0, 0>(L, t2, G.stride, op, om, d);
+#pragma unroll
+  for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
   double S5[5];
   sums_from_a<N>(d, L, S5);
   Macro mac = macro_from_sums(L, S5, G.err);
