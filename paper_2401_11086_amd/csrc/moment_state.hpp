@@ -333,23 +333,26 @@ struct LineTaps {
   int gp[Taps1D<Q1>::p + 1], gm[Taps1D<Q1>::p + 1];         // -1 inside, else the ghost column
 };
 
-// Moment field a of group (BY, BZ) at one tap source (ghost value past a tube's end).
-template <bool SHOCK>
-__device__ __forceinline__ double line_tap(const float* __restrict__ row, unsigned off, int g,
-                                           const float* __restrict__ ghost_col, bool any_ghost) {
+// Moment field a of group (BY, BZ) at one tap source (ghost value past a tube's end).  GHOST is
+// set when some node of the wave pulls from beyond its tube's ends (a wave-uniform choice made
+// once per kernel, so that the taps themselves carry no branch and their loads stay in flight
+// together).
+template <bool GHOST>
+__device__ __forceinline__ float line_tap(const float* __restrict__ row, unsigned off, int g,
+                                          const float* __restrict__ ghost_col) {
   float v = load_at(row, off);
-  if (SHOCK && any_ghost) {
+  if constexpr (GHOST) {
     const float gv = ghost_col[g < 0 ? 0 : g];
     v = g < 0 ? v : gv;
   }
-  return static_cast<double>(v);
+  return v;
 }
 
 // One tap pair's contribution to group (BY, BZ): he[b] = He_b(c_t), rw[a] = Rw_a(c_t) (FP64),
 // pair false for the centre tap.
-template <int N, bool SHOCK, int BY, int BZ>
+template <int N, bool GHOST, int BY, int BZ>
 __device__ __forceinline__ void line_tap_pair(const float* __restrict__ src, long long stride,
-                                              const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                              const float* __restrict__ ghost_m, int n_ghost,
                                               unsigned op, int gp, unsigned om, int gm, bool pair,
                                               const double (&he)[N + 1], const double (&rw)[N + 1], double* acc) {
   constexpr int NO = N - BY - BZ;
@@ -359,9 +362,11 @@ __device__ __forceinline__ void line_tap_pair(const float* __restrict__ src, lon
     const int field = midx(a, BY, BZ);
     const float* __restrict__ row = src + static_cast<size_t>(field) * stride;
     const float* __restrict__ gcol = ghost_m + static_cast<size_t>(field) * n_ghost;
-    const double vp = line_tap<SHOCK>(row, op, gp, gcol, any_ghost);
-    const double vm = pair ? line_tap<SHOCK>(row, om, gm, gcol, any_ghost) : 0.0;
-    const double s = vp + vm, dd = vp - vm;
+    // fold in FP32: exact where the two sources agree (a uniform state stays uniform), unbiased
+    // elsewhere, and the loads in flight stay one register each
+    const float vp = line_tap<GHOST>(row, op, gp, gcol);
+    const float vm = pair ? line_tap<GHOST>(row, om, gm, gcol) : 0.f;
+    const double s = static_cast<double>(vp + vm), dd = static_cast<double>(vp - vm);
     // K_{ba} uses s when a + b is even, d when odd
     ev = fma(rw[a], (a & 1) ? dd : s, ev);
     od = fma(rw[a], (a & 1) ? s : dd, od);
@@ -370,10 +375,10 @@ __device__ __forceinline__ void line_tap_pair(const float* __restrict__ src, lon
   for (int b = 0; b <= NO; ++b) acc[b] = fma(he[b], (b & 1) ? od : ev, acc[b]);
 }
 
-template <int Q1, int N, bool SHOCK, int BY, int BZ>
+template <int Q1, int N, bool GHOST, int BY, int BZ>
 __device__ __forceinline__ void line_group(const LatticeConst& L, const float* __restrict__ src, long long stride,
-                                           const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
-                                           const LineTaps<Q1>& T, double (&d)[n_moments(N)]) {
+                                           const float* __restrict__ ghost_m, int n_ghost,
+                                           const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
   using S = Taps1D<Q1>;
   constexpr int NO = N - BY - BZ;
   constexpr int p = Q1 / 2;
@@ -388,28 +393,30 @@ __device__ __forceinline__ void line_group(const LatticeConst& L, const float* _
       he[n] = L.He64[p + t][n];
       rw[n] = L.Rw64[p + t][n];
     }
-    line_tap_pair<N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T.op[t], T.gp[t], T.om[t], T.gm[t],
+    line_tap_pair<N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T.op[t], T.gp[t], T.om[t], T.gm[t],
                                     t > 0, he, rw, acc);
   }
-  // pin the sums, and fence the loads after every kGroupsPerPhase groups (as in pass x)
+  // pin the sums, and fence the loads after every kGroupsPerPhase groups; the moments wait for
+  // the collision as float32 (as in pass x)
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
-    asm volatile("" : "+v"(acc[b]));
-    d[midx(b, BY, BZ)] = acc[b];
+    float v = static_cast<float>(acc[b]);
+    asm volatile("" : "+v"(v));
+    a32[midx(b, BY, BZ)] = v;
   }
   if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
-template <int Q1, int N, bool SHOCK, int BY, int BZ>
+template <int Q1, int N, bool GHOST, int BY, int BZ>
 __device__ __forceinline__ void line_groups(const LatticeConst& L, const float* __restrict__ src, long long stride,
-                                            const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
-                                            const LineTaps<Q1>& T, double (&d)[n_moments(N)]) {
+                                            const float* __restrict__ ghost_m, int n_ghost,
+                                            const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      line_group<Q1, N, SHOCK, BY, BZ>(L, src, stride, ghost_m, n_ghost, any_ghost, T, d);
-      line_groups<Q1, N, SHOCK, BY, BZ + 1>(L, src, stride, ghost_m, n_ghost, any_ghost, T, d);
+      line_group<Q1, N, GHOST, BY, BZ>(L, src, stride, ghost_m, n_ghost, T, a32);
+      line_groups<Q1, N, GHOST, BY, BZ + 1>(L, src, stride, ghost_m, n_ghost, T, a32);
     } else {
-      line_groups<Q1, N, SHOCK, BY + 1, 0>(L, src, stride, ghost_m, n_ghost, any_ghost, T, d);
+      line_groups<Q1, N, GHOST, BY + 1, 0>(L, src, stride, ghost_m, n_ghost, T, a32);
     }
   }
 }
@@ -425,15 +432,15 @@ struct LaneTap {
   double he[N + 1], rw[N + 1];        // He_b(c_t), Rw_a(c_t) of the lane's tap (zero beyond the taps)
 };
 
-template <int Q1, int N, bool SHOCK, int BY, int BZ>
+template <int Q1, int N, bool GHOST, int BY, int BZ>
 __device__ __forceinline__ void line_group_lane(const float* __restrict__ src, long long stride,
-                                                const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                                const float* __restrict__ ghost_m, int n_ghost,
                                                 const LaneTap<N>& T, double (&d)[n_moments(N)]) {
   constexpr int NO = N - BY - BZ;
   double acc[NO + 1];
 #pragma unroll
   for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
-  line_tap_pair<N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T.op, T.gp, T.om, T.gm, T.pair, T.he,
+  line_tap_pair<N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T.op, T.gp, T.om, T.gm, T.pair, T.he,
                                   T.rw, acc);
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
@@ -443,16 +450,16 @@ __device__ __forceinline__ void line_group_lane(const float* __restrict__ src, l
   if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
 }
 
-template <int Q1, int N, bool SHOCK, int BY, int BZ>
+template <int Q1, int N, bool GHOST, int BY, int BZ>
 __device__ __forceinline__ void line_groups_lane(const float* __restrict__ src, long long stride,
-                                                 const float* __restrict__ ghost_m, int n_ghost, bool any_ghost,
+                                                 const float* __restrict__ ghost_m, int n_ghost,
                                                  const LaneTap<N>& T, double (&d)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      line_group_lane<Q1, N, SHOCK, BY, BZ>(src, stride, ghost_m, n_ghost, any_ghost, T, d);
-      line_groups_lane<Q1, N, SHOCK, BY, BZ + 1>(src, stride, ghost_m, n_ghost, any_ghost, T, d);
+      line_group_lane<Q1, N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T, d);
+      line_groups_lane<Q1, N, GHOST, BY, BZ + 1>(src, stride, ghost_m, n_ghost, T, d);
     } else {
-      line_groups_lane<Q1, N, SHOCK, BY + 1, 0>(src, stride, ghost_m, n_ghost, any_ghost, T, d);
+      line_groups_lane<Q1, N, GHOST, BY + 1, 0>(src, stride, ghost_m, n_ghost, T, d);
     }
   }
 }
@@ -494,8 +501,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
       source(x - S::e[t] - L.k[0], T.op[t], T.gp[t]);
       source(x + S::e[t] - L.k[0], T.om[t], T.gm[t]);
     }
-    const bool any_ghost = SHOCK && __any(ghost);
-    line_groups<Q1, N, SHOCK, 0, 0>(L, src, A.stride, ghost_m, A.n_ghost, any_ghost, T, d);
+    float a32[M];
+    if (SHOCK && __any(ghost)) line_groups<Q1, N, SHOCK, 0, 0>(L, src, A.stride, ghost_m, A.n_ghost, T, a32);
+    else line_groups<Q1, N, false, 0, 0>(L, src, A.stride, ghost_m, A.n_ghost, T, a32);
+#pragma unroll
+    for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
   } else {
     static_assert(LPN > S::p, "one tap pair per lane");
     LaneTap<N> T;
@@ -517,8 +527,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
     T.pair = t > 0;
     source(x - e - L.k[0], T.op, T.gp);
     source(x + e - L.k[0], T.om, T.gm);
-    const bool any_ghost = SHOCK && __any(ghost);
-    line_groups_lane<Q1, N, SHOCK, 0, 0>(src, A.stride, ghost_m, A.n_ghost, any_ghost, T, d);
+    if (SHOCK && __any(ghost)) line_groups_lane<Q1, N, SHOCK, 0, 0>(src, A.stride, ghost_m, A.n_ghost, T, d);
+    else line_groups_lane<Q1, N, false, 0, 0>(src, A.stride, ghost_m, A.n_ghost, T, d);
     group_allreduce<LPN, M>(d);
   }
   double S5[5];
