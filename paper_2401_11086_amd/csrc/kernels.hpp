@@ -485,6 +485,8 @@ LBSMRT_PHASE void gather_project64(const LatticeConst& L, const StepArgs& A,
 // Per-slab source of the additive collision (no addition for the regularised rebuild).
 struct NoAdd {
   static constexpr bool active = false;
+  template <int Q1>
+  __device__ void line(int, float (&)[Q1]) const {}
   __device__ double operator()(int, int) const { return 0.0; }
 };
 struct NoAddSource {
@@ -510,6 +512,20 @@ struct PulledSlab {
       v = ghost ? gv : v;
     }
     return static_cast<double>(v);
+  }
+  // the pulled values of z line iy, all loaded before the line's stores (the compiler cannot
+  // move a load past a store it does not know to be disjoint)
+  __device__ void line(int iy, float (&g)[Q1]) const {
+#pragma unroll
+    for (int iz = 0; iz < Q1; ++iz)
+      g[iz] = load_at(fx + static_cast<size_t>(iy * Q1 + iz) * stride, xoff + P->yo[iy] + P->zo[iz]);
+    if (SHOCK && any_ghost) {
+#pragma unroll
+      for (int iz = 0; iz < Q1; ++iz) {
+        const float gv = load_at(ghosts + static_cast<size_t>(iy * Q1 + iz) * n_ghost, goff);
+        g[iz] = ghost ? gv : g[iz];
+      }
+    }
   }
 };
 template <int Q1, bool SHOCK>
@@ -541,11 +557,20 @@ __device__ __forceinline__ void fold_line_store(const LatticeConst& L, const dou
                                                 float* __restrict__ line_base, long long stride, unsigned off,
                                                 const SL& add = SL{}, int iy = 0) {
   constexpr int p = Q1 / 2;
+  // the additive source's line is loaded ahead of the stores where the registers allow it (up to
+  // seven points per axis); nine-point lines load each value as it is added
+  constexpr bool kAhead = SL::active && Q1 <= 7;
+  float g[Q1];
+  if constexpr (kAhead) add.line(iy, g);
+  auto pulled = [&](int iz) -> double {
+    if constexpr (kAhead) return static_cast<double>(g[iz]);
+    else return add(iy, iz);
+  };
   {
     double s = 0.0;
 #pragma unroll
     for (int az = 0; az <= N; az += 2) s = fma(v[az], L.Rw64[p][az], s);
-    if constexpr (SL::active) s += add(iy, p);
+    if constexpr (SL::active) s += pulled(p);
     store_pop<NT>(line_base + static_cast<size_t>(p) * stride, off, static_cast<float>(s));
   }
 #pragma unroll
@@ -558,8 +583,8 @@ __device__ __forceinline__ void fold_line_store(const LatticeConst& L, const dou
     }
     double hi = e + o, lo = e - o;
     if constexpr (SL::active) {
-      hi += add(iy, p + j);
-      lo += add(iy, p - j);
+      hi += pulled(p + j);
+      lo += pulled(p - j);
     }
     store_pop<NT>(line_base + static_cast<size_t>(p + j) * stride, off, static_cast<float>(hi));
     store_pop<NT>(line_base + static_cast<size_t>(p - j) * stride, off, static_cast<float>(lo));
