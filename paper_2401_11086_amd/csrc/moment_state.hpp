@@ -66,13 +66,14 @@ struct MsGeom {
 };
 
 // March of one line: outputs at positions p0 .. p0 + T - 1 (< len) of the line whose position q
-// has byte offset base + q * step.  Inputs: fields fin[a], a < nf (the 1D index a of the
+// has byte offset base + q * step.  Inputs: fields fin[a], a < NF (the 1D index a of the
 // convolved axis); outputs: fields fout[b], b < no (1D index b).
-template <int Q1, int N>
+template <int Q1, int N, int NF>
 __device__ __forceinline__ void march_line(const MomentTables64& K, const float* __restrict__ in,
                                            float* __restrict__ out, long long stride, const int (&fin)[N + 1],
-                                           int nf, const int (&fout)[N + 1], int no, unsigned base, unsigned step,
+                                           const int (&fout)[N + 1], int no, unsigned base, unsigned step,
                                            int len, int p0, int T, int kshift) {
+  constexpr int nf = NF;
   using S = Taps1D<Q1>;
   constexpr int H = S::H;
   constexpr int W = 2 * H + 1;   // T is a multiple of W (checked by the host)
@@ -142,6 +143,19 @@ __device__ __forceinline__ void march_line(const MomentTables64& K, const float*
   }
 }
 
+// The input count as a compile-time constant (a uniform switch per line), so that the march
+// carries no per-field guards and its work scales with the fields it actually reads.
+template <int Q1, int N, int NF = N + 1>
+__device__ __forceinline__ void march_line_n(const MomentTables64& K, const float* __restrict__ in,
+                                             float* __restrict__ out, long long stride, const int (&fin)[N + 1],
+                                             int nf, const int (&fout)[N + 1], int no, unsigned base, unsigned step,
+                                             int len, int p0, int T, int kshift) {
+  if constexpr (NF >= 1) {
+    if (nf == NF) march_line<Q1, N, NF>(K, in, out, stride, fin, fout, no, base, step, len, p0, T, kshift);
+    else march_line_n<Q1, N, NF - 1>(K, in, out, stride, fin, nf, fout, no, base, step, len, p0, T, kshift);
+  }
+}
+
 // Pass z: a'[ax, ay, az] -> t1[pair(ax, ay) (N+1) + bz].  One work-item per z line (x, y), the
 // lines numbered x fastest over the plane (so a wave reads contiguous 256 B); grid
 // (ceil(nx ny / 256), ceil(nz / T)), each work-item marching T rows.
@@ -162,7 +176,7 @@ __global__ __launch_bounds__(256) void k_ms_pass_z(MomentTables64 K, MsGeom G, c
       for (int a = 0; a <= N; ++a) fin[a] = midx(ax, ay, a <= N - ax - ay ? a : 0);
 #pragma unroll
       for (int b = 0; b <= N; ++b) fout[b] = pair_pos(ax, ay) * (N + 1) + b;
-      march_line<Q1, N>(K, m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, T, G.k[2]);
+      march_line_n<Q1, N>(K, m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, T, G.k[2]);
     }
 }
 
@@ -188,7 +202,7 @@ __global__ __launch_bounds__(256) void k_ms_pass_y(MomentTables64 K, MsGeom G, c
       for (int a = 0; a <= N; ++a) fin[a] = pair_pos(ax, a <= N - ax ? a : 0) * (N + 1) + bz;
 #pragma unroll
       for (int b = 0; b <= N; ++b) fout[b] = ax * P2 + pair_pos(b <= N - bz ? b : 0, bz);
-      march_line<Q1, N>(K, t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, T, G.k[1]);
+      march_line_n<Q1, N>(K, t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, T, G.k[1]);
     }
 }
 
