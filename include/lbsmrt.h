@@ -215,8 +215,10 @@ lbsmrt_status lbsmrt_set_tau(lbsmrt_ctx* ctx, const double* tau);
  * along z, y and x; the state moves M floats per node instead of Q.  On line domains
  * (ny = nz = 1: shock tubes, rings) the y and z stages are the identity, because the
  * quadrature is exact to degree 2N, and the step is the x-stage alone, with the moments of
- * the fixed end states as ghosts.  Results agree with lbsmrt_step on the expanded state up to
- * float32 rounding of m instead of f. */
+ * the fixed end states as ghosts.  The taps run in FP64 with FP64 tables (each +-e pair of
+ * sources folded in float32), so mass, momentum and energy are conserved up to the float32
+ * rounding of m.  Results agree with lbsmrt_step on the expanded state up to float32 rounding
+ * of m instead of f. */
 
 /* Sizes of the moment-state buffers in floats: m_len = M * f_stride (one state) and
  * work_len (scratch of lbsmrt_step_moment_state, 2 (N+1)^2 (N+2)/2 rows of f_stride; 0 when

@@ -17,10 +17,12 @@
 // (W = 2 max|e| + 1), so every input row is read once per line chunk of T rows (T a multiple of
 // W, chosen by the host so that the launch has enough waves).  Pass x reads its row's shifted
 // neighbours directly (same cache lines as the row itself).  Every pass applies a tap pair +-e_t
-// factored through the populations: the rebuilt values F(+-e_t) = sum_a Rw_a(c_t) v_a are
-// folded by parity (K(-e) = (-1)^(a+b) K(e)) and projected with He_b(c_t), in FP64 with FP64
-// tables, so the quadrature identity sum_e K_{b a}(e) = delta_ab, and with it the conservation
-// of mass, momentum and energy, holds up to the float32 storage of the fields.
+// factored through the populations (K(-e) = (-1)^(a+b) K(e)): the two sources are folded by
+// parity in float32, v(x - e) + v(x + e) and v(x - e) - v(x + e) (exact where they agree, so a
+// uniform state stays uniform), and F = sum_a Rw_a(c_t) fold_a and its projection with
+// He_b(c_t) run in FP64 with FP64 tables, so the quadrature identity sum_e K_{b a}(e) =
+// delta_ab, and with it the conservation of mass, momentum and energy, holds up to the float32
+// storage of the fields.
 #pragma once
 #include "kernels.hpp"
 
@@ -334,11 +336,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
 // the step is the x-stage on the moment fields themselves, followed by the collision.  Pulls
 // from beyond a shock tube's ends read the moments of its fixed end states.
 //
-// The x-stage runs in FP64 and factored through the populations: for each tap pair +-e_t the
-// rebuilt populations F(+-e_t) = sum_a Rw_a(c_t) m_a(x -+ e_t) (eq:fi) are formed, folded by
-// parity, and projected with He_b(c_t) (eq:an).  With FP64 tables the quadrature identity holds
-// to FP64 rounding, so a tube conserves mass, momentum and energy up to the float32 storage of
-// the moments (FP32 taps drift a steady shock by ~1e-6 of the mass per step).
+// The x-stage is factored through the populations as in the box passes: for each tap pair +-e_t
+// the two sources are folded by parity in float32, the rebuilt population of the fold (eq:fi)
+// is formed and projected with He_b(c_t) (eq:an) in FP64 with FP64 tables.  The quadrature
+// identity then holds to FP64 rounding, so a tube conserves mass, momentum and energy up to the
+// float32 storage of the moments (float32 tables drift a steady shock by ~1e-6 of the mass per
+// step).
 
 // Sources of the x taps of one node: byte offset into a moment row, or a ghost column.
 template <int Q1>

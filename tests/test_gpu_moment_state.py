@@ -300,8 +300,9 @@ def test_line_batch_equals_separate_contexts(torch):
 
 @pytest.mark.parametrize("stencil,N", [(D1Q7, 4), (D1Q9, 5)], ids=["q343_n4", "q729_n5"])
 def test_line_lanes_per_node_agree(torch, stencil, N):
-    """Eight lanes per node (one tap pair each, DPP group sums) against one lane per node: the
-    same step up to the order of the FP32 tap sums."""
+    """Eight lanes per node (one tap pair each, DPP group sums in FP64) against one lane per
+    node (x-stage moments rounded to float32 before the collision): the same step up to that
+    rounding and the order of the FP64 sums."""
     lat, fields = _line_case(stencil, N, [(3.0, 150)])
     n = lat.n_nodes
     m0 = _noisy_moments(torch, lat, fields, seed=35)
