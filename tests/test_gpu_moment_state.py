@@ -338,3 +338,45 @@ def test_box_moment_state_conserves_mass_momentum_energy(torch):
     print(f"moment-state box, per-node drift of mass, momentum, energy over 50 steps: {drift}")
     # tap tables rounded to float32 break the exact sum rule of the taps and drift mass by ~6e-6
     assert np.all(drift < 1e-7), drift
+
+
+UNIFORM_STATE = (1.1, (0.04, -0.03, 0.02), 0.97)     # rho, u, theta
+UNIFORM_CASES = [
+    ("box_q343_n4", D1Q7, 4, (12, 10, 9), 1),
+    ("box_q729_n5", D1Q9, 5, (11, 9, 13), 1),
+    ("ring_q343_n4", D1Q7, 4, (50, 1, 1), 1),
+    ("ring_q729_n5", D1Q9, 5, (50, 1, 1), 1),
+    ("tube_q729_n5", D1Q9, 5, "tube", 1),              # end states equal to the state
+    ("tube_q729_n5_8lanes", D1Q9, 5, "tube", 8),
+]
+
+
+@pytest.mark.parametrize("name,stencil,N,shape,lanes", UNIFORM_CASES, ids=[c[0] for c in UNIFORM_CASES])
+def test_uniform_state_is_a_fixed_point(torch, name, stencil, N, shape, lanes):
+    """A uniform equilibrium is a fixed point of the step: the taps of every axis sum to the
+    identity (the quadrature is exact to degree 2N) and the collision leaves an equilibrium
+    where it is, so 100 steps move no moment by more than a few float32 ulps (the stored state
+    is the float32 rounding of the equilibrium, which the first steps relax).  Tap tables
+    rounded to float32 break the identity and move such a state by ~1e-7 of its moments per
+    step, 1e-5 over these steps."""
+    rho, u, theta = UNIFORM_STATE
+    if shape == "tube":
+        dom = dict(nx=70, ny=1, nz=1, bc_x=1, rho_in=rho, u_in=u, theta_in=theta, rho_out=rho, u_out=u,
+                   theta_out=theta, tau_scale=1.0)
+        lat = _line_lattice([dom], stencil, N, (0, 0, 0))
+    else:
+        lat, _, _ = _lattice(stencil, N, shape)
+    if lanes > 1:
+        lat.set_launch("direct", 0, 64, lanes)
+    n = lat.n_nodes
+    f = np.empty((5, n))
+    f[0], f[1], f[2], f[3], f[4] = rho, u[0], u[1], u[2], theta
+    m0 = lat.equilibrium_moments(torch.tensor(f, dtype=torch.float64, device="cuda"))
+    m = lat.step_moment_state(m0.clone(), lat.new_moment_state(), lat.new_moment_work(), 100)
+    lat.sync()
+    a, b = m0[:, :n].double(), m[:, :n].double()
+    err = float((b - a).abs().max() / a.abs().max())
+    spread = float((b - b[:, :1]).abs().max() / a.abs().max())
+    print(f"{name}: uniform equilibrium after 100 steps moved by {err:.2e}, non-uniformity {spread:.2e}")
+    assert err < 1e-6, err
+    assert spread == 0.0, spread       # every node sees the same arithmetic
