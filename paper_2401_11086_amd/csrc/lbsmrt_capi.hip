@@ -61,7 +61,7 @@ struct lbsmrt_ctx {
   bool ms_ok = false;
   bool ms_lines = false;
   float* d_ghost_m = nullptr;        // [M][n_ghost] moments of the end states (line domains)
-  MomentTables64 ms_tab{};          // 1D tables of the non-negative taps
+  MomentTables64 ms_tab{};          // 1D tap tables, checked against the compiled ones
 };
 
 namespace {
@@ -232,9 +232,9 @@ struct Launch {
       const long long lz = static_cast<long long>(G.nx) * G.ny, ly = static_cast<long long>(G.nx) * G.nz;
       const int Tz = ms_chunk(lz, G.nz), Ty = ms_chunk(ly, G.ny);
       hipLaunchKernelGGL((k_ms_pass_z<Q1, N>), dim3(static_cast<unsigned>((lz + 255) / 256), (G.nz + Tz - 1) / Tz),
-                         dim3(256), 0, s, c->ms_tab, G, src, t1, Tz);
+                         dim3(256), 0, s, G, src, t1, Tz);
       hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
-                         dim3(256), 0, s, c->ms_tab, G, t1, t2, Ty);
+                         dim3(256), 0, s, G, t1, t2, Ty);
       hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
                          G, t2, dst);
     }
@@ -270,6 +270,21 @@ struct Launch {
       const int p = Q1 / 2;
       for (int t = 0; t <= Taps1D<Q1>::p; ++t)
         if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
+      return true;
+    }
+  }
+  // The context's tap tables agree with the compiled ones of passes z and y (with these taps the
+  // quadrature is unique, so every entry is the same up to the rounding of the host arithmetic).
+  static bool ms_std_match(const lbsmrt_ctx* c) {
+    if constexpr (!kFull) {
+      return false;
+    } else {
+      auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-13 * std::max(1.0, std::fabs(b)); };
+      for (int t = 0; t <= Taps1D<Q1>::p; ++t)
+        for (int n = 0; n <= N; ++n)
+          if (!close(c->ms_tab.He[t][n], MsStdTables<Q1>::He[t][n]) ||
+              !close(c->ms_tab.Rw[t][n], MsStdTables<Q1>::Rw[t][n]))
+            return false;
       return true;
     }
   }
@@ -551,6 +566,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       c->ms_tab.He[t][n] = L.He64[p + t][n];
       c->ms_tab.Rw[t][n] = L.Rw64[p + t][n];
     }
+  dispatch(c->Q1, c->N, [&](auto l) { c->ms_ok = c->ms_ok && decltype(l)::ms_std_match(c); });
+  c->ms_lines = c->ms_lines && c->ms_ok;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return LBSMRT_E_HIP; }

@@ -25,6 +25,7 @@
 // storage of the fields.
 #pragma once
 #include "kernels.hpp"
+#include "ms_std_tables.hpp"
 
 namespace lbsmrt {
 
@@ -59,6 +60,15 @@ struct MomentTables64 {
   double Rw[kMsMaxTaps][kMaxN + 1];
 };
 
+// Tap table entries of passes z and y: compile-time constants (the host has checked that they
+// agree with the context's tables; with these taps the quadrature is unique), which the
+// compiler rematerialises with scalar moves instead of holding up to 60 FP64 values in scalar
+// registers and spilling them.
+template <int Q1>
+__device__ __forceinline__ double tab_he(int t, int n) { return MsStdTables<Q1>::He[t][n]; }
+template <int Q1>
+__device__ __forceinline__ double tab_rw(int t, int n) { return MsStdTables<Q1>::Rw[t][n]; }
+
 struct MsGeom {
   int nx, ny, nz;
   int k[3];            // frame shift (integer), the pull source is x - e - k
@@ -71,7 +81,7 @@ struct MsGeom {
 // has byte offset base + q * step.  Inputs: fields fin[a], a < NF (the 1D index a of the
 // convolved axis); outputs: fields fout[b], b < no (1D index b).
 template <int Q1, int N, int NF>
-__device__ __forceinline__ void march_line(const MomentTables64& K, const float* __restrict__ in,
+__device__ __forceinline__ void march_line(const float* __restrict__ in,
                                            float* __restrict__ out, long long stride, const int (&fin)[N + 1],
                                            const int (&fout)[N + 1], int no, unsigned base, unsigned step,
                                            int len, int p0, int T, int kshift) {
@@ -116,9 +126,9 @@ __device__ __forceinline__ void march_line(const MomentTables64& K, const float*
           double c = 0.0;
 #pragma unroll
           for (int a = 0; a <= N; a += 2)
-            if (a < nf) c = fma(K.Rw[0][a], static_cast<double>(ring[(jj + H) % W][a]), c);
+            if (a < nf) c = fma(tab_rw<Q1>(0, a), static_cast<double>(ring[(jj + H) % W][a]), c);
 #pragma unroll
-          for (int b = 0; b <= N; b += 2) acc[b] = fma(K.He[0][b], c, acc[b]);
+          for (int b = 0; b <= N; b += 2) acc[b] = fma(tab_he<Q1>(0, b), c, acc[b]);
         }
 #pragma unroll
         for (int t = 1; t <= S::p; ++t) {
@@ -130,11 +140,11 @@ __device__ __forceinline__ void march_line(const MomentTables64& K, const float*
             const float vp = ring[(jj + H - S::e[t]) % W][a];
             const float vm = ring[(jj + H + S::e[t]) % W][a];
             const double sm = static_cast<double>(vp + vm), df = static_cast<double>(vp - vm);
-            ev = fma(K.Rw[t][a], (a & 1) ? df : sm, ev);
-            od = fma(K.Rw[t][a], (a & 1) ? sm : df, od);
+            ev = fma(tab_rw<Q1>(t, a), (a & 1) ? df : sm, ev);
+            od = fma(tab_rw<Q1>(t, a), (a & 1) ? sm : df, od);
           }
 #pragma unroll
-          for (int b = 0; b <= N; ++b) acc[b] = fma(K.He[t][b], (b & 1) ? od : ev, acc[b]);
+          for (int b = 0; b <= N; ++b) acc[b] = fma(tab_he<Q1>(t, b), (b & 1) ? od : ev, acc[b]);
         }
         const unsigned off = base + static_cast<unsigned>(pos) * step;
 #pragma unroll
@@ -148,13 +158,13 @@ __device__ __forceinline__ void march_line(const MomentTables64& K, const float*
 // The input count as a compile-time constant (a uniform switch per line), so that the march
 // carries no per-field guards and its work scales with the fields it actually reads.
 template <int Q1, int N, int NF = N + 1>
-__device__ __forceinline__ void march_line_n(const MomentTables64& K, const float* __restrict__ in,
+__device__ __forceinline__ void march_line_n(const float* __restrict__ in,
                                              float* __restrict__ out, long long stride, const int (&fin)[N + 1],
                                              int nf, const int (&fout)[N + 1], int no, unsigned base, unsigned step,
                                              int len, int p0, int T, int kshift) {
   if constexpr (NF >= 1) {
-    if (nf == NF) march_line<Q1, N, NF>(K, in, out, stride, fin, fout, no, base, step, len, p0, T, kshift);
-    else march_line_n<Q1, N, NF - 1>(K, in, out, stride, fin, nf, fout, no, base, step, len, p0, T, kshift);
+    if (nf == NF) march_line<Q1, N, NF>(in, out, stride, fin, fout, no, base, step, len, p0, T, kshift);
+    else march_line_n<Q1, N, NF - 1>(in, out, stride, fin, nf, fout, no, base, step, len, p0, T, kshift);
   }
 }
 
@@ -162,7 +172,7 @@ __device__ __forceinline__ void march_line_n(const MomentTables64& K, const floa
 // lines numbered x fastest over the plane (so a wave reads contiguous 256 B); grid
 // (ceil(nx ny / 256), ceil(nz / T)), each work-item marching T rows.
 template <int Q1, int N>
-__global__ __launch_bounds__(256) void k_ms_pass_z(MomentTables64 K, MsGeom G, const float* __restrict__ m,
+__global__ __launch_bounds__(256) void k_ms_pass_z(MsGeom G, const float* __restrict__ m,
                                                    float* __restrict__ t1, int T) {
   const int line = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
   if (line >= G.nx * G.ny) return;
@@ -178,14 +188,14 @@ __global__ __launch_bounds__(256) void k_ms_pass_z(MomentTables64 K, MsGeom G, c
       for (int a = 0; a <= N; ++a) fin[a] = midx(ax, ay, a <= N - ax - ay ? a : 0);
 #pragma unroll
       for (int b = 0; b <= N; ++b) fout[b] = pair_pos(ax, ay) * (N + 1) + b;
-      march_line_n<Q1, N>(K, m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, T, G.k[2]);
+      march_line_n<Q1, N>(m, t1, G.stride, fin, N - ax - ay + 1, fout, N + 1, base, step, G.nz, z0, T, G.k[2]);
     }
 }
 
 // Pass y: t1[pair(ax, ay) (N+1) + bz] -> t2[ax P2 + pair(by, bz)].  One work-item per y line
 // (x, z), x fastest; grid (ceil(nx nz / 256), ceil(ny / T)).
 template <int Q1, int N>
-__global__ __launch_bounds__(256) void k_ms_pass_y(MomentTables64 K, MsGeom G, const float* __restrict__ t1,
+__global__ __launch_bounds__(256) void k_ms_pass_y(MsGeom G, const float* __restrict__ t1,
                                                    float* __restrict__ t2, int T) {
   constexpr int P2 = n_sym(N);
   const int line = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(256) void k_ms_pass_y(MomentTables64 K, MsGeom G, c
       for (int a = 0; a <= N; ++a) fin[a] = pair_pos(ax, a <= N - ax ? a : 0) * (N + 1) + bz;
 #pragma unroll
       for (int b = 0; b <= N; ++b) fout[b] = ax * P2 + pair_pos(b <= N - bz ? b : 0, bz);
-      march_line_n<Q1, N>(K, t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, T, G.k[1]);
+      march_line_n<Q1, N>(t1, t2, G.stride, fin, N - ax + 1, fout, N - bz + 1, base, step, G.ny, y0, T, G.k[1]);
     }
 }
 
