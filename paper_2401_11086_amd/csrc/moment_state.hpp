@@ -60,7 +60,7 @@ struct MomentTables64 {
   double Rw[kMsMaxTaps][kMaxN + 1];
 };
 
-// Tap table entries of passes z and y: compile-time constants (the host has checked that they
+// Tap table entries of every moment-state pass: compile-time constants (the host has checked that they
 // agree with the context's tables; with these taps the quadrature is unique), which the
 // compiler rematerialises with scalar moves instead of holding up to 60 FP64 values in scalar
 // registers and spilling them.
@@ -241,7 +241,6 @@ __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __re
   using S = Taps1D<Q1>;
   constexpr int P2 = n_sym(N);
   constexpr int NO = N - BY - BZ;
-  constexpr int p = Q1 / 2;
   const float* __restrict__ src[N + 1];
 #pragma unroll
   for (int a = 0; a <= N; ++a) src[a] = t2 + static_cast<size_t>(a * P2 + pair_pos(BY, BZ)) * stride;
@@ -251,9 +250,9 @@ __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __re
   {
     double c = 0.0;                           // centre tap: even orders only
 #pragma unroll
-    for (int a = 0; a <= N; a += 2) c = fma(L.Rw64[p][a], static_cast<double>(load_at(src[a], op[0])), c);
+    for (int a = 0; a <= N; a += 2) c = fma(tab_rw<Q1>(0, a), static_cast<double>(load_at(src[a], op[0])), c);
 #pragma unroll
-    for (int b = 0; b <= NO; b += 2) acc[b] = fma(L.He64[p][b], c, acc[b]);
+    for (int b = 0; b <= NO; b += 2) acc[b] = fma(tab_he<Q1>(0, b), c, acc[b]);
   }
 #pragma unroll
   for (int t = 1; t <= S::p; ++t) {
@@ -264,11 +263,11 @@ __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __re
       const float vp = load_at(src[a], op[t]);
       const float vm = load_at(src[a], om[t]);
       const double sm = static_cast<double>(vp + vm), df = static_cast<double>(vp - vm);
-      ev = fma(L.Rw64[p + t][a], (a & 1) ? df : sm, ev);
-      od = fma(L.Rw64[p + t][a], (a & 1) ? sm : df, od);
+      ev = fma(tab_rw<Q1>(t, a), (a & 1) ? df : sm, ev);
+      od = fma(tab_rw<Q1>(t, a), (a & 1) ? sm : df, od);
     }
 #pragma unroll
-    for (int b = 0; b <= NO; ++b) acc[b] = fma(L.He64[p + t][b], (b & 1) ? od : ev, acc[b]);
+    for (int b = 0; b <= NO; ++b) acc[b] = fma(tab_he<Q1>(t, b), (b & 1) ? od : ev, acc[b]);
   }
   // Finish each group before later loads: the empty asm statements pin the sums here and fence
   // the loads every kGroupsPerPhase groups, otherwise every loaded value stays live until the
@@ -408,7 +407,6 @@ __device__ __forceinline__ void line_group(const LatticeConst& L, const float* _
                                            const LineTaps<Q1>& T, float (&a32)[n_moments(N)]) {
   using S = Taps1D<Q1>;
   constexpr int NO = N - BY - BZ;
-  constexpr int p = Q1 / 2;
   double acc[NO + 1];
 #pragma unroll
   for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
@@ -417,8 +415,8 @@ __device__ __forceinline__ void line_group(const LatticeConst& L, const float* _
     double he[N + 1], rw[N + 1];
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
-      he[n] = L.He64[p + t][n];
-      rw[n] = L.Rw64[p + t][n];
+      he[n] = tab_he<Q1>(t, n);
+      rw[n] = tab_rw<Q1>(t, n);
     }
     line_tap_pair<N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T.op[t], T.gp[t], T.om[t], T.gm[t],
                                     t > 0, he, rw, acc);
@@ -500,7 +498,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
     float* __restrict__ dst) {
   using S = Taps1D<Q1>;
   constexpr int M = n_moments(N);
-  constexpr int p = Q1 / 2;
   const BlockDev bd = A.blocks[blockIdx.x];
   const DomainDev D = A.doms[bd.dom];
   const int x = bd.first + static_cast<int>(threadIdx.x) / LPN;
@@ -542,11 +539,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
     for (int j = 1; j <= S::p; ++j) e = t == j ? S::e[j] : e;
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
-      double h = L.He64[p][n], r = L.Rw64[p][n];
+      double h = tab_he<Q1>(0, n), r = tab_rw<Q1>(0, n);
 #pragma unroll
       for (int j = 1; j <= S::p; ++j) {
-        h = t == j ? L.He64[p + j][n] : h;
-        r = t == j ? L.Rw64[p + j][n] : r;
+        h = t == j ? tab_he<Q1>(j, n) : h;
+        r = t == j ? tab_rw<Q1>(j, n) : r;
       }
       T.he[n] = sub <= S::p ? h : 0.0;          // lanes beyond the taps contribute nothing
       T.rw[n] = r;
