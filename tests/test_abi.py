@@ -66,3 +66,29 @@ def test_binding_fails_loudly_without_gpu():
     from paper_2401_11086_amd import Lattice
     with pytest.raises(RuntimeError):
         Lattice([1, 2, 3], 9, 4, {(2, 0): 1.0}, [dict(nx=4)])
+
+
+def test_compiled_tap_tables_are_current(lib):
+    """The compile-time FP64 tap tables of the moment-state kernels (ms_std_tables.hpp) hold
+    exactly what their generator computes from the library's quadrature, and they satisfy the
+    quadrature identity sum_e He_b(c_e) w_e He_a(c_e) / a! = delta_ab for a, b <= N (the
+    quadrature is exact to degree 2N) to FP64 rounding, which the conservation of the
+    moment-state step rests on."""
+    import importlib.util
+    path = os.path.join(ROOT, "paper_2401_11086_amd", "csrc")
+    spec = importlib.util.spec_from_file_location("gen_ms_std_tables", os.path.join(path, "gen_ms_std_tables.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    text = open(os.path.join(path, "ms_std_tables.hpp")).read()
+    for q1, N in ((7, 4), (9, 5)):
+        he, rw = gen.table(q1)
+        block = text[text.index(f"struct MsStdTables<{q1}>"):]
+        for name, ref in (("He", he), ("Rw", rw)):
+            m = re.search(name + r"\[\d+\]\[\d+\] = \{(.*?)\};\n", block)
+            vals = [float.fromhex(v) for v in re.findall(r"-?0x[0-9a-f.]+p[+-]\d+", m.group(1))]
+            assert vals == [v for row in ref for v in row], (q1, name)
+        p = len(gen.STENCILS[q1][0])
+        for b in range(N + 1):
+            for a in range(N + 1):
+                s = he[0][b] * rw[0][a] + sum((1 + (-1) ** (a + b)) * he[t][b] * rw[t][a] for t in range(1, p + 1))
+                assert abs(s - (1.0 if a == b else 0.0)) < 1e-13, (q1, b, a, s)
