@@ -80,7 +80,7 @@ def main():
     ap = argparse.ArgumentParser(description="run one shock tube to a steady state on the GPU")
     ap.add_argument("--mach", type=float, default=3.0)
     ap.add_argument("--nx", type=int, default=1000)
-    ap.add_argument("--tau", default="smrt", choices=["smrt", "lumped", "shakhov", "bgk", "reduced"])
+    ap.add_argument("--tau", default="smrt", choices=["smrt", "lumped", "shakhov", "bgk", "reduced", "smrt_exact_kernel"])
     ap.add_argument("--stencil", default="d1q9", choices=["d1q7", "d1q9", "d1q17"])
     ap.add_argument("--order", type=int, default=5)
     ap.add_argument("--max-steps", type=int, default=400000)

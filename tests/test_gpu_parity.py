@@ -258,11 +258,12 @@ def test_box_conserves_mass_momentum_energy(torch, precision):
     assert max(drift) < bound, drift
 
 
-@pytest.mark.parametrize("preset", ["shakhov", "bgk", "lumped", "reduced"])
+@pytest.mark.parametrize("preset", ["shakhov", "bgk", "lumped", "reduced", "smrt_exact_kernel"])
 def test_relaxation_presets_one_step_match_oracle(torch, preset):
-    """Table 4's Shakhov column, BGK, one tau per order and the reduced n=4 variant."""
-    from paper_2401_11086_amd.presets import PRESETS
-    table = {k: v for k, v in PRESETS[preset].items()}
+    """Table 4's Shakhov column, BGK, one tau per order, the reduced n=4 variant and SMRT with
+    the exact r^-5 kernel average (tau*_40, tau*_50, tau*_51 off Table 4), on D3Q729, N = 5."""
+    from paper_2401_11086_amd.presets import preset as get_preset
+    table = {k: v for k, v in get_preset(preset).items()}
     table[(2, 1)] = table[(2, 0)]
     case = shock_case(3.0, 30, D1Q9, 5, table=table)
     lat = _lattice(case, "fp64_contract")

@@ -235,11 +235,12 @@ def test_decomposition_commutes_with_rotations(n):
 
 # ----------------------------------------------------------------------------- Table 4
 
-def _wcu_table():
+def _wcu_table(p2=None):
     """tau*_nm = lambda_{0,2} / lambda_{m, n-2m} from the Wang-Chang--Uhlenbeck eigenvalues of
     Maxwell molecules, lambda_rl ~ < 1 + d_r0 d_l0 - x^(r+l/2) P_l(sqrt x) - s^(r+l/2) P_l(sqrt s) >,
     x = cos^2(chi/2), s = sin^2(chi/2), expressed through p = x s; the kernel enters only
-    through <p^2>/<p> = <sin^4 chi>/(4 <sin^2 chi>), which Table 4 corresponds to at 7/36."""
+    through <p^2>/<p> = <sin^4 chi>/(4 <sin^2 chi>), which Table 4 corresponds to at 7/36
+    (the default); another kernel average p2 gives floats."""
     import sympy as sp
     x, p = sp.symbols('x p')
     s = 1 - x
@@ -256,10 +257,12 @@ def _wcu_table():
             sol = sp.solve(sp.Poly(poly, x).all_coeffs(), cs, dict=True)[0]
             assert sol[cs[0]] == 0
             p1 = sp.Integer(1)
-            p2 = sp.Rational(7, 36)
+            pp = sp.Rational(7, 36) if p2 is None else sp.Float(p2, 30)
             assert sol.get(cs[3], 0) == 0
-            lam[(n, m)] = sol[cs[1]] * p1 + sol[cs[2]] * p2
+            lam[(n, m)] = sol[cs[1]] * p1 + sol[cs[2]] * pp
     assert lam[(2, 1)] == 0          # energy conservation: lambda_10 = 0
+    if p2 is not None:
+        return {k: float(lam[(2, 0)] / v) for k, v in lam.items() if k != (2, 1)}
     return {k: Fraction(str(sp.nsimplify(lam[(2, 0)] / v))) for k, v in lam.items() if k != (2, 1)}
 
 
@@ -271,6 +274,54 @@ def test_table4_follows_from_wang_chang_uhlenbeck_eigenvalues():
             assert O.TAU_STAR_SMRT[(int(n), int(m))] == Fraction(t)
         else:
             assert O.TAU_STAR_SHAKHOV[(int(n), int(m))] == Fraction(t)
+
+
+def _ipl5_average(F):
+    """<F> = int_0^inf F(chi(a)) a da for the r^-5 repulsion, with the deflection written as a
+    complete elliptic integral (scipy), independently of the package's Gauss-Legendre route:
+    chi = pi - 2 sqrt(2) a^2 K(-y0/y1) / sqrt(y1), y0,1 = a^4 (sqrt(1 + 2/a^4) -+ 1)."""
+    from scipy import integrate, special
+
+    def chi(a):
+        a4 = a ** 4
+        root = math.sqrt(1.0 + 2.0 / a4)
+        y0, y1 = a4 * (root - 1.0), a4 * (root + 1.0)
+        return math.pi - 2.0 * math.sqrt(2.0) * a * a * special.ellipk(-y0 / y1) / math.sqrt(y1)
+    val, err = integrate.quad(lambda a: F(chi(a)) * a, 1e-12, np.inf, limit=400, epsabs=1e-13, epsrel=1e-12)
+    return val
+
+
+def test_exact_kernel_collision_integrals_match_chapman_cowling():
+    """The package's deflection quadrature gives A_1(5), A_2(5) as tabulated (3 digits) and as
+    the elliptic-integral route gives them (1e-10)."""
+    from paper_2401_11086_amd import wcu
+    for l, a_pub in ((int(r[0]), float(r[1])) for r in _rows("chapman_cowling_ipl5.txt")):
+        a = wcu.collision_integral_A(l)
+        assert abs(a - a_pub) < 6e-4, (l, a, a_pub)
+        assert abs(a - _ipl5_average(lambda c: 1.0 - math.cos(c) ** l)) < 1e-10
+
+
+def test_exact_kernel_preset_follows_from_wang_chang_uhlenbeck():
+    """tau* of the exact r^-5 kernel: the kernel-independent entries are Table 4's rationals, and
+    tau*_40, tau*_50, tau*_51 are the Wang-Chang--Uhlenbeck ratios at the kernel's own
+    <sin^4 chi> / <sin^2 chi> (0.631, against 7/9 for Table 4)."""
+    from paper_2401_11086_amd import wcu
+    from paper_2401_11086_amd.presets import preset
+    s2 = _ipl5_average(lambda c: math.sin(c) ** 2)
+    s4 = _ipl5_average(lambda c: math.sin(c) ** 4)
+    assert abs(s4 / s2 - 0.6311) < 1e-4 and abs(s4 / s2 - 7 / 9) > 0.1
+    ref = _wcu_table(p2=s4 / (4.0 * s2))
+    got = wcu.tau_star_exact_kernel(5)
+    table4 = _wcu_table()
+    for key, v in ref.items():
+        assert abs(got[key] - v) < 1e-9 * max(1.0, v), key
+        if key not in ((4, 0), (5, 0), (5, 1)):
+            assert abs(got[key] - float(table4[key])) < 1e-10, key
+        else:
+            assert abs(got[key] - float(table4[key])) > 1e-2, key
+    assert {k: float(v) for k, v in preset("smrt_exact_kernel").items()} == \
+        {k: got[k] for k in preset("smrt_exact_kernel")}
+    assert abs(got[(4, 0)] - 0.53387) < 5e-6 and abs(got[(5, 0)] - 0.45812) < 5e-6 and abs(got[(5, 1)] - 0.63680) < 5e-6
 
 
 def test_shakhov_prandtl():
