@@ -455,6 +455,12 @@ def time_batched(torch, n_shocks=64, steps=5000, seed=0):
     out["separate_contexts"] = {"ms_per_step": round(ms_sep, 5), "mlups": round(nodes / (ms_sep / 1e3) / 1e6, 1)}
     out["speedup_batched_vs_separate"] = round(ms_sep / ms, 2)
     _progress(f"separate contexts: {ms_sep * 1e3:.1f} us/step")
+    # every context is destroyed here, while the runtime is up, not at interpreter teardown
+    for one, _, _ in sep:
+        one.close()
+    sep.clear()
+    lat.close()
+    del fa, fb, f0, fl
     return out
 
 
@@ -573,6 +579,9 @@ def main():
         _progress("oracle and GPU on two shock tubes")
         out["cpu_baseline"]["shock_samples"] = shock_samples(torch)
     out["device"] = device_record(torch)
+    lat.close()
+    del fa, fb, cur
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

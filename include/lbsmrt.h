@@ -106,7 +106,8 @@ typedef struct {
   long long f_stride;          /* row stride of every [Q][f_stride] buffer */
   long long f_len;             /* Q * f_stride floats per f or lambda buffer */
   int       n_domains;
-  long long domain_offset[64]; /* first node of each domain (first 64 domains) */
+  long long domain_offset[64]; /* first node of each of the first 64 domains; every domain's
+                                  offset is given by lbsmrt_get_domain_offsets */
 } lbsmrt_info;
 
 /* Build a context: solve the 1D quadrature (smallest positive-weight root),
@@ -119,6 +120,12 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
                                   int n_domains, void* stream, lbsmrt_ctx** out);
 
 lbsmrt_status lbsmrt_get_info(const lbsmrt_ctx* ctx, lbsmrt_info* out);
+
+/* First node of every domain, in the order the domains were given to lbsmrt_init_lattice
+ * (domains are concatenated in node space, each x fastest).  out: host array of `capacity`
+ * entries, filled with min(capacity, n_domains) offsets; *n_written (may be NULL) receives
+ * that count.  E_ARG for a NULL ctx or out, or capacity < 1. */
+lbsmrt_status lbsmrt_get_domain_offsets(const lbsmrt_ctx* ctx, long long* out, int capacity, int* n_written);
 
 /* How lbsmrt_step issues its work (lbsmrt_set_launch):
  *  LBSMRT_LAUNCH_DIRECT      one kernel launch per step over all domains (default);
@@ -253,6 +260,9 @@ lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* ctx, float* m_a, float* m_b, 
 /* Wait for `stream` and report (and clear) the latched device state flag. */
 lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* ctx, void* stream);
 
+/* Free the context's device tables and the context (NULL is a no-op).  Call it while the HIP
+ * runtime is alive: not from process-exit handlers that run after the runtime (or a profiler
+ * attached to it) has shut down.  The caller's buffers are untouched. */
 void lbsmrt_destroy(lbsmrt_ctx* ctx);
 const char* lbsmrt_status_string(lbsmrt_status s);
 

@@ -68,6 +68,8 @@ _SIGS = {
     "lbsmrt_init_lattice": (ctypes.c_int, [ctypes.POINTER(LatticeDesc), ctypes.POINTER(DomainDesc), ctypes.c_int,
                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "lbsmrt_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "lbsmrt_get_domain_offsets": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int)]),
     "lbsmrt_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "lbsmrt_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint,
                                       ctypes.c_void_p]),

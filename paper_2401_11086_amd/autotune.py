@@ -1,6 +1,9 @@
 """Launch autotuner: picks lbsmrt_set_launch's mode, work-group size and lanes per node
 by timing a few steps of the caller's own lattice, and caches the choice in a JSON file
-keyed by device, velocity set, order, precision and problem-size bucket."""
+keyed by device, velocity set, order, precision, collision form, problem-size bucket and a
+digest of the domain geometry (shapes and boundary types), so that a choice made for shock
+tubes is never replayed on periodic domains of the same size."""
+import hashlib
 import json
 import math
 import os
@@ -23,11 +26,22 @@ def _cache_path():
                           os.path.join(os.path.expanduser("~"), ".cache", "lbsmrt", "autotune.json"))
 
 
+def _geometry_digest(lat):
+    """Short digest of every domain's (nx, ny, nz, bc_x), in order."""
+    h = hashlib.sha256()
+    for d in lat.domains:
+        h.update(f"{int(d['nx'])},{int(d.get('ny', 1))},{int(d.get('nz', 1))},{int(d.get('bc_x', 0))};".encode())
+    return h.hexdigest()[:16]
+
+
 def _key(lat):
     props = torch.cuda.get_device_properties(lat.device)
     arch = getattr(props, "gcnArchName", props.name)
     bucket = int(round(math.log2(max(lat.n_nodes, 1))))
-    return f"{arch}|Q{lat.Q}|N{lat.N}|{lat.precision}|nodes2^{bucket}|dom{len(lat.domains)}|lpn"
+    shock = int(any(int(d.get("bc_x", 0)) != 0 for d in lat.domains))
+    form = "rebuilt" if lat.regularized else "additive"
+    return (f"{arch}|Q{lat.Q}|N{lat.N}|{lat.precision}|{form}|nodes2^{bucket}|dom{len(lat.domains)}"
+            f"|shock{shock}|geom{_geometry_digest(lat)}|lpn")
 
 
 def _time(lat, fa, fb, steps):
@@ -56,8 +70,11 @@ def autotune(lat, fa, fb, steps=20, graph_steps=32, use_cache=True):
             cache = {}
     if use_cache and key in cache:
         best = cache[key]
-        lat.set_launch(best["mode"], best["block"], graph_steps, best["lanes_per_node"])
-        return dict(best, cached=True)
+        try:
+            lat.set_launch(best["mode"], best["block"], graph_steps, best["lanes_per_node"])
+            return dict(best, cached=True)
+        except Exception:
+            pass   # a stale or foreign entry: tune again and overwrite it
     trials = []
     for mode, block, lpn in _candidates(lat):
         try:

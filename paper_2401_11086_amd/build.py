@@ -1,4 +1,8 @@
-"""Build the gfx950 shared library liblbsmrt.so in-tree with hipcc."""
+"""Build the gfx950 shared library liblbsmrt.so in-tree with hipcc.
+
+Every translation unit (the C-ABI unit, one launch unit per compiled stencil and order, the host
+set-up) is compiled to an object in parallel, then linked; build() always recompiles."""
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -7,12 +11,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbsmrt.so")
+OBJ = os.path.join(PKG, "_build")
 
-SOURCES = ["lbsmrt_capi.hip", "host_setup.cpp"]
+SOURCES = ["lbsmrt_capi.hip", "launch_q7_n3.hip", "launch_q7_n4.hip", "launch_q9_n4.hip", "launch_q9_n5.hip",
+           "launch_q17_n5.hip", "host_setup.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off: the compiler must not form v_pk_*_f32
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -20,15 +26,33 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source into liblbsmrt.so (always recompiles)."""
-    cmd = [HIPCC, *FLAGS, *extra, *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp"]
+def _compile(src, extra, verbose):
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    return obj, res
+
+
+def build(verbose: bool = False, extra=(), jobs=None) -> str:
+    """Compile every source and link liblbsmrt.so (always recompiles)."""
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda s: _compile(s, extra, verbose), SOURCES))
+    failed = [r for _, r in results if r.returncode != 0]
+    for r in failed:
+        sys.stderr.write(r.stdout + r.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed building liblbsmrt.so")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in results], "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building liblbsmrt.so")
+        raise RuntimeError("linking liblbsmrt.so failed")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

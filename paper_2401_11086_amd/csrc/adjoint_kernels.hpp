@@ -207,7 +207,8 @@ __global__ __launch_bounds__(B) void k_adjoint(LatticeConst L, StepArgs A, const
 // group; writes stage[g][col].  Stage 2 sums the G rows of stage the same way in one group.
 constexpr int kReduceBlocks = 256;
 
-__global__ __launch_bounds__(256) void k_reduce_stage1(const double* __restrict__ partial, int rows, int cols,
+// (internal linkage: every translation unit that launches it holds its own copy)
+static __global__ __launch_bounds__(256) void k_reduce_stage1(const double* __restrict__ partial, int rows, int cols,
                                                        double* __restrict__ stage) {
   __shared__ double red[kTauCols * 256];
   double s[kTauCols];
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void k_loss_seed(LatticeConst L, StepArgs A, c
 
 // Stage 2 for the loss (one column): out[0] (+)= sum over the kReduceBlocks rows of stage.
 // Launch: 1 x kReduceBlocks.
-__global__ __launch_bounds__(kReduceBlocks) void k_reduce_loss(const double* __restrict__ stage,
+static __global__ __launch_bounds__(kReduceBlocks) void k_reduce_loss(const double* __restrict__ stage,
                                                                double* __restrict__ out, int accumulate) {
   __shared__ double red[kReduceBlocks];
   double s[1];

@@ -130,4 +130,53 @@ lbsmrt_status shock_states(double Ma, double gamma, double theta1, double theta2
   return LBSMRT_OK;
 }
 
+// FP32 contractions rebuild f* with float32 1D tables rw (the rounded w_j He_n(c_j)/n!), for
+// which the quadrature identity sum_j He_m(c_j) rw[j][n] = delta_mn holds only to float32
+// rounding: a projection with the exact He_m would then see the rebuilt mass, momentum and
+// energy off by ~1e-8 per step, the same way at every step.  The FP64 sums of the conserved
+// moments use instead the weights hd closest to He_m (m = 0, 1, 2) that are exactly dual to the
+// float32 table: hd = he + rw (rw^T rw)^{-1} (e_m - rw^T he), in long double, refined once.  The
+// 3D rebuild table is the tensor product of the 1D one and so is its dual, so the conserved
+// moments of a rebuilt node come back exactly as they went in.
+void dual_projection_table(const float (*rw)[6], const double (*he)[6], int Q1, int N, double (*hd)[3]) {
+  const int n = N + 1;
+  long double G[6][6];
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      long double s = 0.0L;
+      for (int j = 0; j < Q1; ++j) s += static_cast<long double>(rw[j][a]) * rw[j][b];
+      G[a][b] = s;
+    }
+  for (int m = 0; m < 3 && m <= N; ++m) {
+    long double x[17];
+    for (int j = 0; j < Q1; ++j) x[j] = he[j][m];
+    for (int pass = 0; pass < 2; ++pass) {
+      // residual r_b = delta_mb - sum_j x_j rw[j][b]; solve G y = r; x += rw y
+      long double A[6][7];
+      for (int b = 0; b < n; ++b) {
+        long double s = (b == m) ? 1.0L : 0.0L;
+        for (int j = 0; j < Q1; ++j) s -= x[j] * rw[j][b];
+        for (int c = 0; c < n; ++c) A[b][c] = G[b][c];
+        A[b][n] = s;
+      }
+      for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+          if (fabsl(A[i][c]) > fabsl(A[piv][c])) piv = i;
+        for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
+        for (int i = 0; i < n; ++i) {
+          if (i == c || A[c][c] == 0.0L) continue;
+          const long double f = A[i][c] / A[c][c];
+          for (int k = c; k <= n; ++k) A[i][k] -= f * A[c][k];
+        }
+      }
+      for (int b = 0; b < n; ++b) {
+        const long double y = A[b][b] != 0.0L ? A[b][n] / A[b][b] : 0.0L;
+        for (int j = 0; j < Q1; ++j) x[j] += static_cast<long double>(rw[j][b]) * y;
+      }
+    }
+    for (int j = 0; j < Q1; ++j) hd[j][m] = static_cast<double>(x[j]);
+  }
+}
+
 }  // namespace lbsmrt

@@ -163,7 +163,9 @@ __device__ __forceinline__ int source_x(const LatticeConst& L, const Pull<Q1>& P
 
 // Gather the streamed populations and project them (eq:an), sum-factorised:
 //   a[ax,ay,az] = sum_ix He_ax(c_ix) sum_iy He_ay(c_iy) sum_iz He_az(c_iz) g[ix,iy,iz]
-// plus FP64 sums S = (sum g, sum g e_x, sum g e_y, sum g e_z, sum g |e|^2).
+// in FP32, plus the conserved moments in FP64 through the weights Hd dual to the float32 rebuild
+// table: S = (a_0, a_100, a_010, a_001, a_200 + a_020 + a_002), so that a node rebuilt with the
+// float32 table hands the same rho, j and energy to the next step's projection.
 // The x loop stays rolled (one 2D slab of Q1*Q1 populations per iteration).
 template <int Q1, int N, bool SHOCK>
 __device__ __forceinline__ void gather_project(const LatticeConst& L, const StepArgs& A,
@@ -179,6 +181,7 @@ __device__ __forceinline__ void gather_project(const LatticeConst& L, const Step
     float t2[P2];
 #pragma unroll
     for (int i = 0; i < P2; ++i) t2[i] = 0.f;
+    // per slab: U0 = (0,0), U1y = (1,0), U1z = (0,1), U2 = (2,0) + (0,2) Hermite orders in (y, z)
     double U0 = 0.0, U1y = 0.0, U1z = 0.0, U2 = 0.0;
     const int xs = source_x<Q1>(L, P, ix);
     const float* __restrict__ fx = f + static_cast<size_t>(ix * Q1 * Q1) * A.stride;
@@ -214,21 +217,19 @@ __device__ __forceinline__ void gather_project(const LatticeConst& L, const Step
 #pragma unroll
         for (int n = 0; n <= N; ++n) t1[n] = fmaf(g, L.He[iz][n], t1[n]);
         const double gd = static_cast<double>(g);
-        const double ez = static_cast<double>(L.e[iz]);
-        V0 += gd;
-        V1 = fma(gd, ez, V1);
-        V2 = fma(gd, ez * ez, V2);
+        V0 = fma(gd, L.Hd[iz][0], V0);
+        V1 = fma(gd, L.Hd[iz][1], V1);
+        V2 = fma(gd, L.Hd[iz][2], V2);
       }
 #pragma unroll
       for (int ay = 0; ay <= N; ++ay)
 #pragma unroll
         for (int az = 0; az <= N; ++az)
           if (ay + az <= N) t2[pair_pos(ay, az)] = fmaf(t1[az], L.He[iy][ay], t2[pair_pos(ay, az)]);
-      const double ey = static_cast<double>(L.e[iy]);
-      U0 += V0;
-      U1y = fma(V0, ey, U1y);
-      U1z += V1;
-      U2 += fma(V0, ey * ey, V2);
+      U0 = fma(V0, L.Hd[iy][0], U0);
+      U1y = fma(V0, L.Hd[iy][1], U1y);
+      U1z = fma(V1, L.Hd[iy][0], U1z);
+      U2 = fma(V0, L.Hd[iy][2], fma(V2, L.Hd[iy][0], U2));
     }
     float hx[N + 1];
 #pragma unroll
@@ -240,12 +241,11 @@ __device__ __forceinline__ void gather_project(const LatticeConst& L, const Step
 #pragma unroll
         for (int az = 0; az <= N; ++az)
           if (ax + ay + az <= N) a[midx(ax, ay, az)] = fmaf(t2[pair_pos(ay, az)], hx[ax], a[midx(ax, ay, az)]);
-    const double ex = static_cast<double>(L.e[ix]);
-    S[0] += U0;
-    S[1] = fma(U0, ex, S[1]);
-    S[2] += U1y;
-    S[3] += U1z;
-    S[4] += fma(U0, ex * ex, U2);
+    S[0] = fma(U0, L.Hd[ix][0], S[0]);
+    S[1] = fma(U0, L.Hd[ix][1], S[1]);
+    S[2] = fma(U1y, L.Hd[ix][0], S[2]);
+    S[3] = fma(U1z, L.Hd[ix][0], S[3]);
+    S[4] = fma(U0, L.Hd[ix][2], fma(U2, L.Hd[ix][0], S[4]));
   }
 }
 
@@ -801,13 +801,21 @@ __device__ __forceinline__ void collide_stream_node(const LatticeConst& L, const
     }
   } else {
     float a[M];
-    gather_project<Q1, N, SHOCK>(L, A, fsrc, P, a, S);
+    double H[5];
+    gather_project<Q1, N, SHOCK>(L, A, fsrc, P, a, H);
 #pragma unroll
     for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a[i]);
-    d[0] = S[0];            // orders 0 and 1 from the FP64 sums
-    d[1] = L.r * S[1];
-    d[2] = L.r * S[2];
-    d[3] = L.r * S[3];
+    // orders 0 and 1 and the trace of order 2 from the FP64 sums: the FP32 trace would leave a
+    // (2,1) part, which is not relaxed, and re-emit its rounding as energy every step
+    d[0] = H[0];
+    d[1] = H[1];
+    d[2] = H[2];
+    d[3] = H[3];
+    const double dtr = (H[4] - (d[midx(2, 0, 0)] + d[midx(0, 2, 0)] + d[midx(0, 0, 2)])) * (1.0 / 3.0);
+    d[midx(2, 0, 0)] += dtr;
+    d[midx(0, 2, 0)] += dtr;
+    d[midx(0, 0, 2)] += dtr;
+    sums_from_a<N>(d, L, S);
   }
   Macro mac = macro_from_sums(L, S, A.err);
   mac.tsc = P.tsc;

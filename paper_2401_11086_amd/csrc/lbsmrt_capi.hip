@@ -8,61 +8,11 @@
 #include <new>
 #include <vector>
 
+#include "capi_internal.hpp"
 #include "host_setup.hpp"
-#include "adjoint_kernels.hpp"
-#include "kernels.hpp"
-#include "lbsmrt.h"
-#include "moment_state.hpp"
 
 using namespace lbsmrt;
 
-struct lbsmrt_ctx {
-  int device = -1;
-  int Q1 = 0, N = 0, Q = 0, M = 0;
-  double r = 0.0;
-  double w1[17] = {};
-  int e1[17] = {};
-  LatticeConst L{};
-  std::vector<lbsmrt_domain> doms;
-  std::vector<long long> dom_off;
-  long long n_nodes = 0, stride = 0;
-  bool shock = false;
-  int block = 256;
-  int lpn = 1;                       // lanes per node of the step kernel (1; 2, 4 or 8: shocks, FP64)
-  int n_blocks = 0;
-  int n_ghost = 0;
-  DomainDev* d_doms = nullptr;
-  BlockDev* d_blocks = nullptr;
-  float* d_ghost = nullptr;
-  double* d_ghost_fields = nullptr;
-  int* d_err = nullptr;
-  double* d_partial = nullptr;   // [n_blocks_adj][kTauCols] per-block partial sums
-  BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
-  BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
-  BlockDev* d_blocks_adj8 = nullptr; // 8-node work-groups of the adjoint at eight lanes per node
-  int n_blocks_adj4 = 0, n_blocks_adj8 = 0;
-  BlockDev* d_blocks_adjR = nullptr; // 256-node work-groups of the adjoint on periodic domains
-  int n_blocks_adjR = 0;             // (0: not used)
-  bool lpn4_ok = false;              // lanes_per_node > 1 allowed: shock domains, FP64
-                                     // contractions, state below 4 GiB
-  double* d_stage = nullptr;         // [kReduceBlocks][kTauCols] first-stage column sums
-  // launch mode of lbsmrt_step
-  int mode = LBSMRT_LAUNCH_DIRECT;
-  int persistent_grid = 0;           // resident work-groups of the persistent kernel
-  hipGraphExec_t graph = nullptr;    // captured pair of steps for LBSMRT_LAUNCH_GRAPH
-  const float* graph_a = nullptr;
-  const float* graph_b = nullptr;
-  int graph_pairs = 0;
-  int n_blocks_adj = 0;
-  int precision = LBSMRT_FP32;
-  bool additive = false;              // f* = g + R (a' - a) instead of the rebuild (regularized = 0)
-  // moment-state form: one periodic domain (box passes) or line domains only (ny = nz = 1: the
-  // x-stage alone), with a stencil whose taps are compiled
-  bool ms_ok = false;
-  bool ms_lines = false;
-  float* d_ghost_m = nullptr;        // [M][n_ghost] moments of the end states (line domains)
-  MomentTables64 ms_tab{};          // 1D tap tables, checked against the compiled ones
-};
 
 namespace {
 
@@ -82,245 +32,6 @@ double hermite_1d(int n, double x) {
   }
   return h1;
 }
-
-// Launch dispatch over the compiled (Q1, N) pairs.  The 17-point stencil (kFull false) has the
-// forward step with FP64 contractions and the rebuilt collision, the moments and the equilibrium
-// fill only; the API refuses the rest for it before dispatching.
-template <int Q1, int N>
-struct Launch {
-  static constexpr bool kFull = Q1 <= 9;
-  template <int PREC>
-  static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
-    // additive collision: FP64 contractions, one lane per node
-    if constexpr (kFull) {
-      if (PREC == kPrecFp64 && c->additive && c->shock) {
-        hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0,
-                           s, c->L, A, src, dst);
-        return;
-      }
-      if (PREC == kPrecFp64 && c->additive) {
-        hipLaunchKernelGGL((k_collide_stream<Q1, N, false, kPrecFp64, 1, true>), dim3(c->n_blocks), dim3(c->block), 0,
-                           s, c->L, A, src, dst);
-        return;
-      }
-    }
-    if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 8>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
-                         A, src, dst);
-    else if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 4>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
-                         A, src, dst);
-    else if (PREC == kPrecFp64 && c->shock && c->lpn == 2)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 2>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
-                         A, src, dst);
-    else if (c->shock)
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, PREC>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src,
-                         dst);
-    else
-      hipLaunchKernelGGL((k_collide_stream<Q1, N, false, PREC>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L, A, src,
-                         dst);
-  }
-  static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s) {
-    if constexpr (kFull) {
-      if (c->precision == LBSMRT_FP32) {
-        step_p<kPrecFp32>(c, A, src, dst, s);
-        return;
-      }
-    }
-    step_p<kPrecFp64>(c, A, src, dst, s);
-  }
-  template <int PREC, bool SH>
-  static const void* persistent_fn() {
-    return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC>);
-  }
-  static const void* persistent(const lbsmrt_ctx* c) {
-    if constexpr (!kFull) {
-      return nullptr;
-    } else {
-      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8)
-        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 8>);
-      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
-        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
-      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2)
-        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 2>);
-      if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
-      return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
-    }
-  }
-  static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s) {
-    if (c->shock)
-      hipLaunchKernelGGL((k_moments<Q1, N, true>), dim3(c->n_blocks), dim3(c->block / c->lpn), 0, s, c->L, A, f, out, mask,
-                         c->n_nodes);
-    else
-      hipLaunchKernelGGL((k_moments<Q1, N, false>), dim3(c->n_blocks), dim3(c->block / c->lpn), 0, s, c->L, A, f, out, mask,
-                         c->n_nodes);
-  }
-  static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
-                      hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
-      int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
-      if constexpr (N <= 4) {
-        if (!c->shock && c->n_blocks_adjR > 0) {
-          nb = c->n_blocks_adjR;
-          hipLaunchKernelGGL((k_adjoint<Q1, N, false, 1, kAdjRowBlock>), dim3(nb), dim3(kAdjRowBlock),
-                             2 * sizeof(double) * n_moments(N) * kAdjRowBlock, s, c->L, A, f_t, lam_next, lam_t,
-                             c->d_partial);
-          hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
-                             n_tau_slots(N), c->d_stage);
-          hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
-          return;
-        }
-      }
-      if (c->shock && c->lpn == 8)
-        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
-      else if (c->shock && c->lpn == 4)
-        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
-      else if (c->shock)
-        hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
-      else
-        hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
-      hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
-                         n_tau_slots(N), c->d_stage);
-      hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
-    }
-  }
-  // Raise the dynamic LDS limit of the 256-node periodic adjoint (N <= 4); false if refused.
-  static bool allow_row_adjoint() {
-    if constexpr (N <= 4) {
-      const int bytes = static_cast<int>(2 * sizeof(double) * n_moments(N) * kAdjRowBlock);
-      return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint<Q1, N, false, 1, kAdjRowBlock>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-    }
-    return false;
-  }
-  static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
-                        float* lam, hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      if (c->shock)
-        hipLaunchKernelGGL((k_loss_seed<Q1, N, true>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
-                           c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
-      else
-        hipLaunchKernelGGL((k_loss_seed<Q1, N, false>), dim3(c->n_blocks_adj), dim3(64), 0, s, c->L, A, f, target,
-                           c->n_nodes, sc[0], sc[1], sc[2], lam, c->d_partial);
-    }
-  }
-  // Moment-state form.  Line chunk of the z and y passes: a multiple of the tap window W, as long
-  // as possible (the W - 1 halo rows are read again per chunk) while the launch still has about
-  // kMsLanes work-items (4 waves per SIMD of the chip), and at most 8 W.
-  static constexpr int kMsWindow = 2 * Taps1D<Q1>::H + 1;
-  static constexpr long long kMsLanes = 262144;
-  static int ms_chunk(long long lines, int len) {
-    const long long chunks = std::max(1LL, (kMsLanes + lines - 1) / lines);
-    const long long rows = (len + chunks - 1) / chunks;
-    const long long r = std::min(8LL, std::max(1LL, rows / kMsWindow));
-    return static_cast<int>(r) * kMsWindow;
-  }
-  static void ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, float* dst, float* t1, float* t2,
-                      hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      const long long lz = static_cast<long long>(G.nx) * G.ny, ly = static_cast<long long>(G.nx) * G.nz;
-      const int Tz = ms_chunk(lz, G.nz), Ty = ms_chunk(ly, G.ny);
-      hipLaunchKernelGGL((k_ms_pass_z<Q1, N>), dim3(static_cast<unsigned>((lz + 255) / 256), (G.nz + Tz - 1) / Tz),
-                         dim3(256), 0, s, G, src, t1, Tz);
-      hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
-                         dim3(256), 0, s, G, t1, t2, Ty);
-      hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
-                         G, t2, dst);
-    }
-  }
-  // Line domains: eight lanes per node (one tap pair each) when the context splits nodes over
-  // four or more lanes (small tubes), else one.
-  static void ms_line_step(lbsmrt_ctx* c, const StepArgs& A0, const float* src, float* dst, hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      StepArgs A = A0;
-      const bool split = c->lpn >= 4;
-      A.blocks = split ? c->d_blocks_adj8 : c->d_blocks_adj;
-      const int nb = split ? c->n_blocks_adj8 : c->n_blocks_adj;
-      if (split && c->shock)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
-                           c->d_ghost_m, src, dst);
-      else if (split)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 8>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
-                           c->d_ghost_m, src, dst);
-      else if (c->shock)
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
-                           c->d_ghost_m, src, dst);
-      else
-        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
-                           c->d_ghost_m, src, dst);
-    }
-  }
-  static bool ms_taps_match(const lbsmrt_ctx* c) {
-    if constexpr (!kFull) {
-      return false;
-    } else {
-      const int p = Q1 / 2;
-      for (int t = 0; t <= Taps1D<Q1>::p; ++t)
-        if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
-      return true;
-    }
-  }
-  // The context's tap tables agree with the compiled ones of passes z and y (with these taps the
-  // quadrature is unique, so every entry is the same up to the rounding of the host arithmetic).
-  static bool ms_std_match(const lbsmrt_ctx* c) {
-    if constexpr (!kFull) {
-      return false;
-    } else {
-      auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-13 * std::max(1.0, std::fabs(b)); };
-      for (int t = 0; t <= Taps1D<Q1>::p; ++t)
-        for (int n = 0; n <= N; ++n)
-          if (!close(c->ms_tab.He[t][n], MsStdTables<Q1>::He[t][n]) ||
-              !close(c->ms_tab.Rw[t][n], MsStdTables<Q1>::Rw[t][n]))
-            return false;
-      return true;
-    }
-  }
-  static void ms_project(lbsmrt_ctx* c, const float* f, float* m, hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-      hipLaunchKernelGGL((k_ms_project<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, f, m, c->stride, c->n_nodes);
-    }
-  }
-  static void ms_expand(lbsmrt_ctx* c, const float* m, float* f, hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-      hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
-    }
-  }
-  static void ms_equilibrium_into(lbsmrt_ctx* c, const double* fields, long long count, float* m, long long stride,
-                                  hipStream_t s) {
-    const unsigned nb = static_cast<unsigned>((count + 255) / 256);
-    hipLaunchKernelGGL((k_ms_equilibrium<N>), dim3(nb), dim3(256), 0, s, c->L, fields, count, m, stride);
-  }
-  static void ms_equilibrium(lbsmrt_ctx* c, const double* fields, float* m, hipStream_t s) {
-    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-    hipLaunchKernelGGL((k_ms_equilibrium<N>), dim3(nb), dim3(256), 0, s, c->L, fields, c->n_nodes, m, c->stride);
-  }
-  static void equilibrium(lbsmrt_ctx* c, const double* fields, long long count, float* f, long long stride,
-                          hipStream_t s) {
-    const int bs = 256;
-    const long long nb = (count + bs - 1) / bs;
-    hipLaunchKernelGGL((k_equilibrium<Q1, N>), dim3(static_cast<unsigned>(nb)), dim3(bs), 0, s, c->L, fields, count,
-                       f, stride);
-  }
-};
 
 bool supported(int Q1, int N) {
   return (Q1 == 7 && (N == 3 || N == 4)) || (Q1 == 9 && (N == 4 || N == 5)) || (Q1 == 17 && N == 5);
@@ -480,6 +191,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
       L.Rw64[j][n] = c->w1[j] * h / fact;
     }
   }
+  dual_projection_table(L.Rw, L.He64, Q1, c->N, L.Hd);
   L.r = r;
   for (int k = 0; k < 3; ++k) L.k[k] = desc->shift_k[k];
   for (int n = 0; n <= kMaxN; ++n)
@@ -638,6 +350,14 @@ lbsmrt_status lbsmrt_get_info(const lbsmrt_ctx* c, lbsmrt_info* o) {
   o->f_len = c->stride * c->Q;
   o->n_domains = static_cast<int>(c->doms.size());
   for (size_t i = 0; i < c->dom_off.size() && i < 64; ++i) o->domain_offset[i] = c->dom_off[i];
+  return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_get_domain_offsets(const lbsmrt_ctx* c, long long* out, int capacity, int* n_written) {
+  if (!c || !out || capacity < 1) return LBSMRT_E_ARG;
+  const int n = static_cast<int>(std::min<size_t>(static_cast<size_t>(capacity), c->dom_off.size()));
+  for (int i = 0; i < n; ++i) out[i] = c->dom_off[i];
+  if (n_written) *n_written = n;
   return LBSMRT_OK;
 }
 

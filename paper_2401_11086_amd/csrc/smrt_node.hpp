@@ -60,6 +60,7 @@ struct LatticeConst {
   float  Rw[kMaxQ1][kMaxN + 1];   // w_j He_n(c_j) / n!
   double He64[kMaxQ1][kMaxN + 1]; // the same two tables in FP64
   double Rw64[kMaxQ1][kMaxN + 1];
+  double Hd[kMaxQ1][3];           // FP64 projection weights of orders 0..2 dual to the float32 Rw
   int    e[kMaxQ1];               // 1D integers, ascending
   double r;                       // lattice constant c_l
   int    k[3];                    // frame shift, ubar = r k

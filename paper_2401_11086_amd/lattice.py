@@ -1,10 +1,34 @@
 """Python face of the LB-SMRT library: a lattice context over caller-owned
 torch device tensors.  PyTorch supplies device memory and the stream only."""
+import atexit
 import ctypes
+import weakref
 
 import torch
 
 from . import _lib as C
+
+
+# Every open context, so that all are destroyed while the HIP runtime is still up: at interpreter
+# exit the atexit hook runs before module teardown, where __del__ would otherwise free device
+# tables after the runtime (or a profiler attached to it) has been finalised.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    live = list(_LIVE)
+    if not live:
+        return
+    try:
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    for lat in live:
+        try:
+            lat.close()
+        except Exception:
+            pass
 
 
 def _stream_ptr():
@@ -82,8 +106,12 @@ class Lattice:
         self.e1d = [info.e1d[i] for i in range(self.Q1)]
         self.n_nodes = info.n_nodes
         self.f_stride = info.f_stride
-        self.domain_offset = [info.domain_offset[i] for i in range(min(info.n_domains, 64))]
+        offs = (ctypes.c_longlong * info.n_domains)()
+        got = ctypes.c_int()
+        C.check(lib.lbsmrt_get_domain_offsets(h, offs, info.n_domains, ctypes.byref(got)), "lbsmrt_get_domain_offsets")
+        self.domain_offset = [offs[i] for i in range(got.value)]
         self.device = torch.device("cuda", torch.cuda.current_device())
+        _LIVE.add(self)
 
     # -- buffers ------------------------------------------------------------
     def new_state(self):
@@ -203,9 +231,11 @@ class Lattice:
         C.check(C.lib().lbsmrt_sync_status(self._h, _stream_ptr()), "lbsmrt_sync_status")
 
     def close(self):
+        """Destroy the context (its device tables); the caller's buffers are untouched."""
         if getattr(self, "_h", None):
             C.lib().lbsmrt_destroy(self._h)
             self._h = None
+        _LIVE.discard(self)
 
     def __del__(self):
         try:

@@ -56,6 +56,32 @@ def test_batched_equals_separate_contexts(torch):
         assert torch.equal(cur[:, off:off + n], gc[:, :n]), i
 
 
+def test_more_than_64_domains_locate_and_match_separate_contexts(torch):
+    """A batch of 70 short shocks: every domain offset is reported (beyond the 64 held by
+    lbsmrt_info), and every shock equals its own separate context bitwise."""
+    from paper_2401_11086_amd import Lattice
+    rng = np.random.default_rng(4)
+    draws = [(float(rng.uniform(1.2, 2.4)), int(rng.integers(20, 60))) for _ in range(70)]
+    lat, fl, doms, fields, tau = _batch(torch, draws)
+    assert len(lat.domain_offset) == 70
+    assert lat.domain_offset == list(np.cumsum([0] + [d["nx"] for d in doms[:-1]]))
+    fa = lat.equilibrium(fl)
+    fb = lat.new_state()
+    cur = lat.step(fa, fb, 9)
+    lat.sync()
+    for i, (d, f) in enumerate(zip(doms, fields)):
+        one = Lattice([1, 2, 3], 9, 4, tau, [d], shift_k=(1, 0, 0), precision="fp64_contract")
+        one.set_launch("direct", 0, 2, lat.launch_settings()["lanes_per_node"])
+        ga = one.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda"))
+        gb = one.new_state()
+        gc = one.step(ga, gb, 9)
+        one.sync()
+        off, n = lat.domain_offset[i], d["nx"]
+        assert torch.equal(cur[:, off:off + n], gc[:, :n]), i
+        one.close()
+    lat.close()
+
+
 @pytest.mark.parametrize("mode", ["graph", "persistent"])
 def test_launch_modes_match_direct_bitwise(torch, mode):
     lat, fl, doms, fields, tau = _batch(torch, DRAWS)

@@ -123,6 +123,29 @@ def test_autotune_candidates():
     assert len(_candidates(tube64)) == len(CANDIDATES) == 36
 
 
+def test_autotune_key_separates_geometries(monkeypatch):
+    """A tuned choice for shock tubes must not be replayed on periodic domains of the same size
+    (nor across domain shapes or collision forms)."""
+    import types
+
+    import paper_2401_11086_amd.autotune as A
+    monkeypatch.setattr(A.torch.cuda, "get_device_properties", lambda dev: types.SimpleNamespace(
+        name="gfx950", gcnArchName="gfx950"))
+
+    def fake(domains, precision="fp64_contract", regularized=True):
+        lat = _FakeLattice(domains, precision)
+        lat.device, lat.Q, lat.N, lat.regularized = 0, 729, 5, regularized
+        lat.n_nodes = sum(d["nx"] * d.get("ny", 1) * d.get("nz", 1) for d in domains)
+        return lat
+    tubes = fake([dict(nx=600, bc_x=1), dict(nx=424, bc_x=1)])
+    rings = fake([dict(nx=600, bc_x=0), dict(nx=424, bc_x=0)])
+    other = fake([dict(nx=500, bc_x=1), dict(nx=524, bc_x=1)])
+    add = fake([dict(nx=600, bc_x=1), dict(nx=424, bc_x=1)], regularized=False)
+    keys = {A._key(x) for x in (tubes, rings, other, add)}
+    assert len(keys) == 4
+    assert A._key(tubes) == A._key(fake([dict(nx=600, bc_x=1), dict(nx=424, bc_x=1)]))
+
+
 def test_bench_traffic_record_is_keyed_by_sources(tmp_path, monkeypatch):
     import bench
     digest = bench.kernel_source_digest()
