@@ -50,18 +50,29 @@ typedef enum {
   LBSMRT_E_HIP = 4,          /* a HIP runtime call failed */
   LBSMRT_E_NOMEM = 5,        /* device or host allocation failed */
   LBSMRT_E_UNSUPPORTED = 6   /* valid but not built: a (Q1, N) pair with no compiled kernel (built:
-                                D1Q7 with N = 3, 4; D1Q9 with N = 4, 5; D1Q17 with N = 5), the
-                                reserved precision, regularized = 0 with FP32 contractions (or with
+                                D1Q7 with N = 3, 4; D1Q9 with N = 4, 5; D1Q17 with N = 5), a
+                                configuration the split-BF16x3 form does not take (see
+                                lbsmrt_precision), regularized = 0 with FP32 contractions (or with
                                 the adjoint, the persistent launch or the moment state), D1Q17 with
                                 anything but the forward step, moments and equilibrium in FP64
                                 contractions and the rebuilt collision, or a launch setting the
                                 context does not allow */
 } lbsmrt_status;
 
-/* Arithmetic of the projection / rebuild contractions.  The state f is float32 in every mode.
- *  LBSMRT_FP32          FP32 contractions; conserved sums, frame shift and relaxation in FP64.
- *  LBSMRT_SPLIT_BF16X3  reserved (returns LBSMRT_E_UNSUPPORTED).
- *  LBSMRT_FP64_CONTRACT FP64 contractions folded over +-e pairs: the rebuild then conserves
+/* Arithmetic of the projection (eq:an) / rebuild (eq:fi) contractions.  The state f is float32 in
+ * every mode; the conserved sums, frame shift, irreducible split and relaxation run in FP64.
+ *  LBSMRT_FP32          sum-factorised FP32 contractions; the conserved moments (and the order-2
+ *                       trace) are taken in FP64 through weights dual to the float32 rebuild table,
+ *                       so a rebuilt node hands its mass, momentum and energy on exactly.
+ *  LBSMRT_SPLIT_BF16X3  dense contractions on the matrix cores: each operand split into bf16 halves,
+ *                       hi.hi + hi.lo + lo.hi products accumulated in FP32 (v_mfma_f32_32x32x16_bf16);
+ *                       orders 0, 1 and the order-2 trace from FP64 sums, and the rebuild corrected
+ *                       per node so that its conserved sums are exact.  Stencils D1Q7 {0, +-1, +-2,
+ *                       +-3} and D1Q9 {0, +-1, +-2, +-3, +-5} only, the
+ *                       rebuilt collision, one lane per node, 256-item work-groups, direct or graph
+ *                       launches; every periodic domain needs nx % 32 == 0, and one x-slab of the
+ *                       state (Q1^2 f_stride floats) must stay below 4 GiB (E_UNSUPPORTED otherwise).
+ *  LBSMRT_FP64_CONTRACT sum-factorised FP64 contractions folded over +-e pairs: the rebuild conserves
  *                       mass, momentum and energy up to the float32 rounding of the stored f. */
 typedef enum { LBSMRT_FP32 = 0, LBSMRT_SPLIT_BF16X3 = 1, LBSMRT_FP64_CONTRACT = 2 } lbsmrt_precision;
 

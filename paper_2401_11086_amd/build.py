@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "liblbsmrt.so")
 OBJ = os.path.join(PKG, "_build")
 
 SOURCES = ["lbsmrt_capi.hip", "launch_q7_n3.hip", "launch_q7_n4.hip", "launch_q9_n4.hip", "launch_q9_n5.hip",
-           "launch_q17_n5.hip", "host_setup.cpp"]
+           "launch_q17_n5.hip", "host_setup.cpp", "mfma_tables.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

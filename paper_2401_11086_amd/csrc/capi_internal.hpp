@@ -10,6 +10,7 @@
 #include "adjoint_kernels.hpp"
 #include "kernels.hpp"
 #include "lbsmrt.h"
+#include "mfma_bf16x3.hpp"
 #include "moment_state.hpp"
 
 struct lbsmrt_ctx {
@@ -57,7 +58,10 @@ struct lbsmrt_ctx {
   bool ms_ok = false;
   bool ms_lines = false;
   float* d_ghost_m = nullptr;        // [M][n_ghost] moments of the end states (line domains)
-  lbsmrt::MomentTables64 ms_tab{};          // 1D tap tables, checked against the compiled ones
+  lbsmrt::MomentTables64 ms_tab{};
+  // split-BF16x3 contractions: MFMA operand tables and conservation constants (one allocation)
+  void* d_mfma = nullptr;
+  lbsmrt::MfmaArgs mfma{};          // 1D tap tables, checked against the compiled ones
 };
 
 namespace lbsmrt {

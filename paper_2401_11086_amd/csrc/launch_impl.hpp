@@ -47,6 +47,15 @@ void Launch<Q1, N>::step(lbsmrt_ctx* c, const StepArgs& A, const float* src, flo
         step_p<kPrecFp32>(c, A, src, dst, s);
         return;
       }
+      if (c->precision == LBSMRT_SPLIT_BF16X3) {   // 256-item work-groups, 4 waves of 64 nodes
+        if (c->shock)
+          hipLaunchKernelGGL((k_collide_stream_bf16x3<Q1, N, true>), dim3(c->n_blocks), dim3(256), 0, s, c->L, A,
+                             c->mfma, src, dst);
+        else
+          hipLaunchKernelGGL((k_collide_stream_bf16x3<Q1, N, false>), dim3(c->n_blocks), dim3(256), 0, s, c->L, A,
+                             c->mfma, src, dst);
+        return;
+      }
     }
     step_p<kPrecFp64>(c, A, src, dst, s);
   }
@@ -62,6 +71,7 @@ const void* Launch<Q1, N>::persistent(const lbsmrt_ctx* c) {
     if constexpr (!kFull) {
       return nullptr;
     } else {
+      if (c->precision == LBSMRT_SPLIT_BF16X3) return nullptr;
       if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8)
         return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 8>);
       if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)

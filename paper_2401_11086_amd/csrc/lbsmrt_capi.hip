@@ -10,6 +10,7 @@
 
 #include "capi_internal.hpp"
 #include "host_setup.hpp"
+#include "mfma_tables.hpp"
 
 using namespace lbsmrt;
 
@@ -79,6 +80,7 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_blocks_adjR);
   (void)hipFree(c->d_stage);
   (void)hipFree(c->d_ghost_m);
+  (void)hipFree(c->d_mfma);
   delete c;
 }
 
@@ -107,7 +109,8 @@ lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
   if (d->n_abscissa < 1 || d->n_abscissa > 8) return LBSMRT_E_ARG;
   if (d->order_N < 2 || d->order_N > kMaxN) return LBSMRT_E_ARG;
   if (d->regularized != 0 && d->regularized != 1) return LBSMRT_E_ARG;
-  if (d->precision != LBSMRT_FP32 && d->precision != LBSMRT_FP64_CONTRACT) return LBSMRT_E_UNSUPPORTED;
+  if (d->precision != LBSMRT_FP32 && d->precision != LBSMRT_FP64_CONTRACT && d->precision != LBSMRT_SPLIT_BF16X3)
+    return LBSMRT_E_UNSUPPORTED;
   if (d->regularized == 0 && d->precision != LBSMRT_FP64_CONTRACT) return LBSMRT_E_UNSUPPORTED;
   if (!(d->rho_ref > 0.0)) return LBSMRT_E_ARG;
   for (int n = 2; n <= d->order_N; ++n)
@@ -232,6 +235,14 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (off >= (1LL << 30)) { free_ctx(c); return LBSMRT_E_ARG; }   // 32-bit node offsets in the kernels
   c->stride = (off + 63) / 64 * 64;
   c->block = (max_local >= 4096) ? 256 : 64;
+  if (c->precision == LBSMRT_SPLIT_BF16X3) {
+    // the MFMA step takes 256-node work-groups of 32-node tiles, each inside one x row
+    for (int i = 0; i < n_domains; ++i)
+      if (domains[i].bc_x == 0 && domains[i].nx % 32 != 0) { free_ctx(c); return LBSMRT_E_UNSUPPORTED; }
+    // 32-bit byte offsets inside one x-slab (Q1^2 population planes) and across 4 planes (stores)
+    if (static_cast<long long>(c->Q1) * c->Q1 * c->stride * 4 >= (1LL << 32)) { free_ctx(c); return LBSMRT_E_UNSUPPORTED; }
+    c->block = 256;
+  }
   // Shock tubes with few nodes fill a small part of the GPU, and each wavefront's serial work
   // sets the step time: start with several lanes per node there (lbsmrt_set_launch can change it).
   // (the split kernels address a slab by a 32-bit byte offset from the start of f)
@@ -300,6 +311,25 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (hipMalloc(&c->d_stage, sizeof(double) * kTauCols * kReduceBlocks) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (c->ms_lines && hipMalloc(&c->d_ghost_m, sizeof(float) * c->M * c->n_ghost) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
+  if (c->precision == LBSMRT_SPLIT_BF16X3) {
+    // built for the stencils D1Q7 {0, +-1, +-2, +-3} and D1Q9 {0, +-1, +-2, +-3, +-5}
+    bool std_taps = c->Q1 == 7 || c->Q1 == 9;
+    for (int j = 0; std_taps && j < c->Q1; ++j)
+      std_taps = c->e1[j] == (c->Q1 == 7 ? MfmaStencil<7>::e[j] : MfmaStencil<9>::e[j]);
+    if (!std_taps) return fail(LBSMRT_E_UNSUPPORTED);
+    MfmaHostTables mt;
+    if (!build_mfma_tables(c->Q1, c->N, r, c->w1, c->e1, mt)) return fail(LBSMRT_E_QUADRATURE);
+    const size_t pb = mt.proj.size() * 2, rb = mt.rebuild.size() * 2, cb = mt.cons.size() * sizeof(double);
+    if (hipMalloc(&c->d_mfma, pb + rb + cb) != hipSuccess) return fail(LBSMRT_E_NOMEM);
+    char* base = static_cast<char*>(c->d_mfma);
+    if (hipMemcpy(base, mt.proj.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + pb, mt.rebuild.data(), rb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + pb + rb, mt.cons.data(), cb, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(LBSMRT_E_HIP);
+    c->mfma.proj = reinterpret_cast<const u32x4_t*>(base);
+    c->mfma.rebuild = reinterpret_cast<const u32x4_t*>(base + pb);
+    c->mfma.cons = reinterpret_cast<const double*>(base + pb + rb);
+  }
   // ghost states: rows rho, ux, uy, uz, theta, columns (left_i, right_i)
   std::vector<double> gf(5 * c->n_ghost, 0.0);
   for (int i = 0; i < n_domains; ++i) {
@@ -429,7 +459,9 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4 && lanes_per_node != 8)
     return LBSMRT_E_ARG;
   if (lanes_per_node > 1 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
-  if (mode == LBSMRT_LAUNCH_PERSISTENT && (c->additive || c->Q1 > 9)) return LBSMRT_E_UNSUPPORTED;
+  if (mode == LBSMRT_LAUNCH_PERSISTENT && (c->additive || c->Q1 > 9 || c->precision == LBSMRT_SPLIT_BF16X3))
+    return LBSMRT_E_UNSUPPORTED;
+  if (c->precision == LBSMRT_SPLIT_BF16X3 && block_size != 0 && block_size != 256) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;
   drop_graph(c);
   const int bs = block_size != 0 ? block_size : c->block;

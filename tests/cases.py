@@ -66,3 +66,75 @@ def family_error(x_gpu, x_ref, order, rho_ref=1.0, theta_ref=1.0):
     max|x_gpu - x_ref| / max(max|x_ref|, rho_ref theta_ref^(n/2))."""
     scale = max(float(np.abs(x_ref).max()), rho_ref * theta_ref ** (order / 2.0))
     return float(np.abs(np.asarray(x_gpu) - np.asarray(x_ref)).max()) / scale
+
+
+# Largest l1 norm of the coefficients with which a derived observable combines the components of
+# its Hermite family (m = d^(3,0)/D(3,0): 8/5 for m_xxx; R^(4,1) = d^(4,1)/D(4,1): 3 for the
+# off-diagonal components; R^(4,2) = d^(4,2)/D(4,2) = (7/3) tr tr d^(4): 21).  If every component
+# of the family is within tol of its scale, the derived observable is within tol times this norm.
+DERIVED_L1 = {"m": 8.0 / 5.0, "R41": 3.0, "R42": 21.0}
+
+
+def compare_observables(lat, f_gpu, f_oracle, case, tol, derived_implied=False):
+    """Every moment family of the GPU state (lbsmrt_moments) against the oracle's observables of
+    the same state, in the scale-relative sense of family_error; asserts each is within tol and
+    returns them.  derived_implied: hold m, R41 and R42 to the bound that the tolerance of their
+    family implies (tol times DERIVED_L1) instead of tol itself."""
+    from paper_2401_11086_amd import _lib as C
+    mask = C.MOM_BASIC | C.MOM_SIGMA | C.MOM_Q | C.MOM_M3 | C.MOM_DLOCAL | C.MOM_ALAB
+    if case["model"].N >= 4:
+        mask |= C.MOM_R41 | C.MOM_R42
+    g = lat.moments(f_gpu, mask).cpu().numpy()
+    ob = O.observables(f_oracle, case["model"], case["dom"])
+    M = case["model"].M
+    rows = {}
+    r = 0
+    for name, cnt in [("basic", 5), ("sigma", 6), ("q", 3), ("m", 10), ("R41", 6), ("R42", 1), ("d", M), ("a", M)]:
+        if name in ("R41", "R42") and case["model"].N < 4:
+            continue
+        rows[name] = g[r:r + cnt]
+        r += cnt
+    errs = {
+        "rho": family_error(rows["basic"][0], ob["rho"], 0),
+        "u": family_error(rows["basic"][1:4], ob["u"], 1),
+        "theta": family_error(rows["basic"][4], ob["theta"], 2),
+        "sigma": family_error(rows["sigma"], ob["sigma"], 2),
+        "q": family_error(rows["q"], ob["q"], 3),
+        "m": family_error(rows["m"], ob["m"], 3),
+    }
+    if case["model"].N >= 4:
+        errs["R41"] = family_error(rows["R41"], ob["R41"], 4)
+        errs["R42"] = family_error(rows["R42"], ob["R42"], 4)
+    sl = 0
+    for n in range(case["model"].N + 1):
+        cnt = (n + 1) * (n + 2) // 2
+        errs[f"d{n}"] = family_error(rows["d"][sl:sl + cnt], ob["d"][sl:sl + cnt], n)
+        sl += cnt
+    a_ref = O.project(O.stream(f_oracle, case["model"], case["dom"]).reshape(case["model"].vs.Q, -1), case["model"])
+    sl = 0
+    for n in range(case["model"].N + 1):
+        cnt = (n + 1) * (n + 2) // 2
+        errs[f"a{n}"] = family_error(rows["a"][sl:sl + cnt], a_ref[sl:sl + cnt], n)
+        sl += cnt
+    lim = {k: tol * (DERIVED_L1.get(k, 1.0) if derived_implied else 1.0) for k in errs}
+    bad = {k: v for k, v in errs.items() if not v <= lim[k]}
+    assert not bad, f"moment families over {tol}: {bad} (all: {errs})"
+    return errs
+
+
+def normalised(ob_rho, ob_th, ob_q, st):
+    return ((ob_rho - st["rho1"]) / (st["rho2"] - st["rho1"]),
+            (ob_th - st["theta1"]) / (st["theta2"] - st["theta1"]),
+            ob_q / (st["rho1"] * st["theta1"] ** 1.5))
+
+
+def crossing(rho_hat):
+    """Fractional cell index where the normalised density crosses 1/2."""
+    i = int(np.argmax(rho_hat >= 0.5))
+    return i - 1 + (0.5 - rho_hat[i - 1]) / (rho_hat[i] - rho_hat[i - 1])
+
+
+def shift_profile(y, dx):
+    """y(x + dx) by linear interpolation (ends held)."""
+    x = np.arange(len(y), dtype=float)
+    return np.interp(x + dx, x, y)

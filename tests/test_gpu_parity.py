@@ -11,6 +11,10 @@ import oracle as O
 from paper_2401_11086_amd import workloads as W
 
 from cases import D1Q7, D1Q9, box_case, family_error, oracle_state_from_gpu, shock_case
+from cases import compare_observables as _compare_observables
+from cases import crossing as _crossing
+from cases import normalised as _normalised
+from cases import shift_profile as _shift_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -54,48 +58,6 @@ def _gpu_moments(lat, f, mask):
     return lat.moments(f, mask).cpu().numpy()
 
 
-def _compare_observables(lat, f_gpu, f_oracle, case, tol):
-    from paper_2401_11086_amd import _lib as C
-    mask = C.MOM_BASIC | C.MOM_SIGMA | C.MOM_Q | C.MOM_M3 | C.MOM_DLOCAL | C.MOM_ALAB
-    if case["model"].N >= 4:
-        mask |= C.MOM_R41 | C.MOM_R42
-    g = _gpu_moments(lat, f_gpu, mask)
-    ob = O.observables(f_oracle, case["model"], case["dom"])
-    M = case["model"].M
-    rows = {}
-    r = 0
-    for name, cnt in [("basic", 5), ("sigma", 6), ("q", 3), ("m", 10), ("R41", 6), ("R42", 1), ("d", M), ("a", M)]:
-        if name in ("R41", "R42") and case["model"].N < 4:
-            continue
-        rows[name] = g[r:r + cnt]
-        r += cnt
-    errs = {
-        "rho": family_error(rows["basic"][0], ob["rho"], 0),
-        "u": family_error(rows["basic"][1:4], ob["u"], 1),
-        "theta": family_error(rows["basic"][4], ob["theta"], 2),
-        "sigma": family_error(rows["sigma"], ob["sigma"], 2),
-        "q": family_error(rows["q"], ob["q"], 3),
-        "m": family_error(rows["m"], ob["m"], 3),
-    }
-    if case["model"].N >= 4:
-        errs["R41"] = family_error(rows["R41"], ob["R41"], 4)
-        errs["R42"] = family_error(rows["R42"], ob["R42"], 4)
-    sl = 0
-    for n in range(case["model"].N + 1):
-        cnt = (n + 1) * (n + 2) // 2
-        errs[f"d{n}"] = family_error(rows["d"][sl:sl + cnt], ob["d"][sl:sl + cnt], n)
-        sl += cnt
-    a_ref = O.project(O.stream(f_oracle, case["model"], case["dom"]).reshape(case["model"].vs.Q, -1), case["model"])
-    sl = 0
-    for n in range(case["model"].N + 1):
-        cnt = (n + 1) * (n + 2) // 2
-        errs[f"a{n}"] = family_error(rows["a"][sl:sl + cnt], a_ref[sl:sl + cnt], n)
-        sl += cnt
-    bad = {k: v for k, v in errs.items() if not v <= tol}
-    assert not bad, f"moment families over {tol}: {bad} (all: {errs})"
-    return errs
-
-
 CASES = {
     "shock_q343_n4_ma1.2": lambda: shock_case(1.2, 200, D1Q7, 4),
     "shock_q729_n5_ma3": lambda: shock_case(3.0, 120, D1Q9, 5),
@@ -133,31 +95,13 @@ def test_one_step_matches_oracle(torch, name, precision):
     _compare_observables(lat, out, fo1, case, TOL_STEP)
 
 
-def _normalised(ob_rho, ob_th, ob_q, st):
-    return ((ob_rho - st["rho1"]) / (st["rho2"] - st["rho1"]),
-            (ob_th - st["theta1"]) / (st["theta2"] - st["theta1"]),
-            ob_q / (st["rho1"] * st["theta1"] ** 1.5))
-
-
-def _crossing(rho_hat):
-    """Fractional cell index where the normalised density crosses 1/2."""
-    i = int(np.argmax(rho_hat >= 0.5))
-    return i - 1 + (0.5 - rho_hat[i - 1]) / (rho_hat[i] - rho_hat[i - 1])
-
-
-def _shift_profile(y, dx):
-    """y(x + dx) by linear interpolation (ends held)."""
-    x = np.arange(len(y), dtype=float)
-    return np.interp(x + dx, x, y)
-
-
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_shock_trajectory_1000_steps_matches_oracle(torch, precision):
-    """Ma = 1.2, D3Q343, N = 4, Nx = 200: normalised rho, theta, q_x every 100 steps.
-    A shock between two fixed Maxwellian ends is translation-neutral: FP32
-    round-off in the mass balance moves it without a restoring force, so the
-    profiles are compared after aligning the rho_hat = 1/2 crossing; the raw
-    (unaligned) difference and the drift are reported."""
+    """Ma = 1.2, D3Q343, N = 4, Nx = 200: normalised rho, theta, q_x every 100 steps, raw
+    (unaligned) within 1e-4 for both contraction precisions.  A shock between two fixed
+    Maxwellian ends is translation-neutral, so any bias in the mass balance would move it
+    without a restoring force; the shock offset and the profile difference after aligning the
+    rho_hat = 1/2 crossing are printed beside the raw difference."""
     from paper_2401_11086_amd import _lib as C
     case = shock_case(1.2, 200, D1Q7, 4)
     lat = _lattice(case, precision)
@@ -182,10 +126,10 @@ def test_shock_trajectory_1000_steps_matches_oracle(torch, precision):
         e = max(float(np.abs(_shift_profile(a, dx) - b)[5:-5].max()) for a, b in zip(gn, on))
         print(f"step {100 * (seg + 1)}: raw {raw:.2e}, shock offset {dx:+.2e} cells, aligned {e:.2e}, "
               f"mass gpu-oracle {float(g[0].sum() - ob['rho'].sum()):+.2e}")
-        worst = max(worst, e)
+        worst = max(worst, raw)
+        assert raw < TOL_PROFILE, (seg, raw)
         assert e < TOL_PROFILE, (seg, e)
-        assert raw < 10 * TOL_PROFILE, (seg, raw)
-    print(f"worst aligned normalised-profile error over 1000 steps: {worst:.3e}")
+    print(f"worst raw normalised-profile error over 1000 steps: {worst:.3e}")
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
@@ -253,9 +197,10 @@ def test_box_conserves_mass_momentum_energy(torch, precision):
     n = lat.n_nodes
     drift = [abs(b - a) / n for a, b in zip(t0, t1)]
     print(f"{precision}: per-node drift of mass, momentum, energy over 50 steps: {drift}")
-    # FP32 contractions carry the float32 rounding of the rebuild tables (~2e-8 relative per step)
-    bound = 2e-7 if precision == "fp64_contract" else 2e-5
-    assert max(drift) < bound, drift
+    # both forms hand the conserved moments of a rebuilt node exactly to the next projection
+    # (FP64 tables, or weights dual to the float32 rebuild table): what is left is the float32
+    # rounding of the stored populations
+    assert max(drift) < 2e-7, drift
 
 
 @pytest.mark.parametrize("preset", ["shakhov", "bgk", "lumped", "reduced", "smrt_exact_kernel"])
@@ -327,7 +272,8 @@ def test_steady_state_driver_reaches_rankine_hugoniot_plateaus(torch):
 def test_box32_200_steps_both_precisions_match_oracle(torch):
     """The 32^3 sub-run of the box workload (Kn = 0.05 on its own edge, 16 Fourier modes per
     field): 200 steps of the oracle from the GPU's FP32 initial state, against 200 GPU steps in
-    each contraction precision, every moment family within 1e-4 at steps 100 and 200."""
+    each contraction precision; every moment family is printed and held within 1e-5 of its
+    scale at steps 100 and 200."""
     case = box_case(32, D1Q7, 4, n_ref=32)
     lats, cur = {}, {}
     for precision in PRECISIONS:
@@ -343,9 +289,9 @@ def test_box32_200_steps_both_precisions_match_oracle(torch):
         for _ in range(100):
             fo = O.step(fo, case["model"], case["dom"])
         for precision, lat in lats.items():
-            errs = _compare_observables(lat, cur[precision][0], fo, case, TOL_PROFILE)
-            print(f"32^3 box, step {100 * (seg + 1)}, {precision}: worst family {max(errs, key=errs.get)} "
-                  f"{max(errs.values()):.2e}")
+            errs = _compare_observables(lat, cur[precision][0], fo, case, TOL_STEP)
+            print(f"32^3 box, step {100 * (seg + 1)}, {precision}: " +
+                  ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
 
 
 def test_steady_profile_matches_oracle_steady_profile(torch):
