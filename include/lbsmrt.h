@@ -49,7 +49,7 @@ typedef enum {
   LBSMRT_E_STATE = 3,        /* a node left rho > 0, 0 < theta < 2, or became non-finite */
   LBSMRT_E_HIP = 4,          /* a HIP runtime call failed */
   LBSMRT_E_NOMEM = 5,        /* device or host allocation failed */
-  LBSMRT_E_UNSUPPORTED = 6   /* valid but not built: a (Q1, N) pair with no compiled kernel (built:
+  LBSMRT_E_UNSUPPORTED = 6,  /* valid but not built: a (Q1, N) pair with no compiled kernel (built:
                                 D1Q7 with N = 3, 4; D1Q9 with N = 4, 5; D1Q17 with N = 5), a
                                 configuration the split-BF16x3 form does not take (see
                                 lbsmrt_precision), regularized = 0 with FP32 contractions (or with
@@ -57,6 +57,8 @@ typedef enum {
                                 anything but the forward step, moments and equilibrium in FP64
                                 contractions and the rebuilt collision, or a launch setting the
                                 context does not allow */
+  LBSMRT_E_LIMIT = 7         /* the problem exceeds the fixed scratch of an allocation-free entry
+                                point (lbsmrt_step_adjoint_noalloc) */
 } lbsmrt_status;
 
 /* Arithmetic of the projection (eq:an) / rebuild (eq:fi) contractions.  The state f is float32 in
@@ -209,6 +211,24 @@ lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* ctx, const double* fields, float* f
  * E_UNSUPPORTED for an additive-collision context (regularized = 0).  Asynchronous. */
 lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* ctx, const float* f_t, const float* lam_next,
                                   float* lam_t, double* dL_dtau, void* stream);
+
+/* lbsmrt_step_adjoint without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, results and summation order as lbsmrt_step_adjoint (bit-identical lam_t and
+ * dL_dtau increment); the dL/dtau reduction partials go to a fixed 8 MiB device array of the
+ * library (one per GPU, held until the process ends) instead of the context's buffers.  It calls
+ * no hipMalloc, hipFree or allocating library routine.
+ * Limit: n_tau_slots * (G + 256) doubles <= 2^20, where n_tau_slots = 3, 6, 9 for N = 3, 4, 5 and
+ * G is the adjoint's work-group count (nodes / 256 on periodic domains with N <= 4, else
+ * nodes / 64 at one lane per node, nodes / 16 and nodes / 8 at four and eight lanes, each domain
+ * rounded up): about 44 million nodes for a periodic box with N = 4 (256^3 fits) and 7.4 million
+ * for N = 5.
+ * Larger contexts get E_LIMIT.  The context's device must be the current device (else E_ARG).
+ * Every call on one GPU shares the array, so calls that overlap on that GPU (other streams,
+ * other threads, other contexts) race: serialise them.  Nothing in the array needs to start at
+ * zero; each call writes every entry it reads.  Asynchronous. */
+lbsmrt_status lbsmrt_step_adjoint_noalloc(lbsmrt_ctx* ctx, const float* f_t, const float* lam_next,
+                                          float* lam_t, double* dL_dtau, void* stream);
 
 /* Seed of the adjoint for the shock-profile misfit
  *   L = sum_x [ s_rho^2 (rho - rho*)^2 + s_theta^2 (theta - theta*)^2 + s_q^2 (q_x - q_x*)^2 ]

@@ -9,7 +9,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbsmrt.so")
 
-OK, E_ARG, E_QUADRATURE, E_STATE, E_HIP, E_NOMEM, E_UNSUPPORTED = range(7)
+OK, E_ARG, E_QUADRATURE, E_STATE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_LIMIT = range(8)
 FP32, SPLIT_BF16X3, FP64_CONTRACT = 0, 1, 2
 LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_PERSISTENT = 0, 1, 2
 MOM_BASIC, MOM_SIGMA, MOM_Q, MOM_M3, MOM_R41, MOM_R42, MOM_DLOCAL, MOM_ALAB = (1, 2, 4, 8, 16, 32, 64, 128)
@@ -77,6 +77,8 @@ _SIGS = {
     "lbsmrt_equilibrium": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbsmrt_step_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "lbsmrt_step_adjoint_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbsmrt_loss_seed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),

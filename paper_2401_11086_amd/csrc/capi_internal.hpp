@@ -66,6 +66,13 @@ struct lbsmrt_ctx {
 
 namespace lbsmrt {
 
+// Work-groups of the adjoint launch, one row of dL/dtau partial sums each: the 256-node periodic
+// grid when the context has one, else the grid of its lanes-per-node setting.
+inline int adjoint_groups(const lbsmrt_ctx* c) {
+  if (!c->shock && c->n_blocks_adjR > 0) return c->n_blocks_adjR;
+  return c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
+}
+
 // Launch dispatch over the compiled (Q1, N) pairs.  The 17-point stencil (kFull false) has the
 // forward step with FP64 contractions and the rebuilt collision, the moments and the equilibrium
 // fill only; the API refuses the rest for it before dispatching.
@@ -79,8 +86,10 @@ struct Launch {
   static const void* persistent_fn();
   static const void* persistent(const lbsmrt_ctx* c);
   static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s);
+  // Adjoint step and its dL/dtau reduction: per-work-group partials (adjoint_groups(c) rows of
+  // n_tau_slots(N)) in partial, the first-stage column sums (kReduceBlocks rows) in stage.
   static void adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
-                      hipStream_t s);
+                      double* partial, double* stage, hipStream_t s);
   // Raise the dynamic LDS limit of the 256-node periodic adjoint (N <= 4); false if refused.
   static bool allow_row_adjoint();
   static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,

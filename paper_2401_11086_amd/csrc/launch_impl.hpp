@@ -95,39 +95,37 @@ void Launch<Q1, N>::moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, do
 
 template <int Q1, int N>
 void Launch<Q1, N>::adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, const float* lam_next, float* lam_t,
-                      hipStream_t s) {
+                            double* partial, double* stage, hipStream_t s) {
     if constexpr (!kFull) {
       return;
     } else {
       const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
-      int nb = c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
+      const int nb = adjoint_groups(c);
       if constexpr (N <= 4) {
         if (!c->shock && c->n_blocks_adjR > 0) {
-          nb = c->n_blocks_adjR;
           hipLaunchKernelGGL((k_adjoint<Q1, N, false, 1, kAdjRowBlock>), dim3(nb), dim3(kAdjRowBlock),
                              2 * sizeof(double) * n_moments(N) * kAdjRowBlock, s, c->L, A, f_t, lam_next, lam_t,
-                             c->d_partial);
-          hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
-                             n_tau_slots(N), c->d_stage);
-          hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
+                             partial);
+          hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, partial, nb, n_tau_slots(N),
+                             stage);
+          hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, stage, A.dtau);
           return;
         }
       }
       if (c->shock && c->lpn == 8)
         hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
+                           lam_t, partial);
       else if (c->shock && c->lpn == 4)
         hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
+                           lam_t, partial);
       else if (c->shock)
         hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
+                           lam_t, partial);
       else
         hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, c->d_partial);
-      hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, c->d_partial, nb,
-                         n_tau_slots(N), c->d_stage);
-      hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, c->d_stage, A.dtau);
+                           lam_t, partial);
+      hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, partial, nb, n_tau_slots(N), stage);
+      hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, stage, A.dtau);
     }
   }
 

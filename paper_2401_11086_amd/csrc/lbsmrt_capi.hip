@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -13,6 +14,13 @@
 #include "mfma_tables.hpp"
 
 using namespace lbsmrt;
+
+// Reduction scratch of lbsmrt_step_adjoint_noalloc: the per-work-group dL/dtau partial sums
+// followed by the first-stage column sums.  One copy per GPU, at its own address, held until the
+// process ends; calls on one GPU share it.  Host code never passes this name to a kernel: it
+// uses the address scratch_address returns for the device.
+constexpr size_t kScratchDoubles = size_t(1) << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 
 namespace {
@@ -84,6 +92,32 @@ void free_ctx(lbsmrt_ctx* c) {
   delete c;
 }
 
+// Device address of scratch per device ordinal, looked up once per device with that device
+// current (lbsmrt_init_lattice); nullptr until then or if the lookup failed.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Looks up the address of scratch on device dev, which must be current: E_HIP if
+// hipGetSymbolAddress fails.  Ordinals from kMaxDevices on are skipped (their contexts cannot use
+// the allocation-free entry point).
+lbsmrt_status scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return LBSMRT_OK;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return LBSMRT_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return LBSMRT_E_HIP;
+  g_scratch[dev] = static_cast<double*>(p);
+  return LBSMRT_OK;
+}
+
+double* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[dev];
+}
+
 // Eligible contexts start with L lanes per node while nodes * L stays within 65536 work-items
 // (1024 wavefronts, one per SIMD of the chip): 8 up to 8192 nodes, 4 up to 16384, else 1.
 constexpr long long kSplitWorkItems = 65536;
@@ -121,6 +155,27 @@ lbsmrt_status validate_desc(const lbsmrt_lattice_desc* d) {
   return LBSMRT_OK;
 }
 
+
+lbsmrt_status adjoint_check(const lbsmrt_ctx* c, const float* f_t, const float* lam_next, const float* lam_t,
+                            const double* dL_dtau) {
+  if (!c || !f_t || !lam_next || !lam_t || !dL_dtau) return LBSMRT_E_ARG;
+  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
+  if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
+  if (c->additive) return LBSMRT_E_UNSUPPORTED;
+  return LBSMRT_OK;
+}
+
+lbsmrt_status adjoint_launch(lbsmrt_ctx* c, const float* f_t, const float* lam_next, float* lam_t, double* dL_dtau,
+                             double* partial, double* stage, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  StepArgs A = step_args(c);
+  A.blocks = c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj);
+  if (!c->shock && c->n_blocks_adjR > 0) A.blocks = c->d_blocks_adjR;
+  A.dtau = dL_dtau;
+  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, partial, stage, s); });
+  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -134,6 +189,7 @@ const char* lbsmrt_status_string(lbsmrt_status s) {
     case LBSMRT_E_HIP: return "HIP runtime error";
     case LBSMRT_E_NOMEM: return "out of memory";
     case LBSMRT_E_UNSUPPORTED: return "unsupported configuration";
+    case LBSMRT_E_LIMIT: return "problem too large for the fixed scratch of an allocation-free entry point";
   }
   return "unknown status";
 }
@@ -294,6 +350,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return LBSMRT_E_HIP; }
+  // device address of the allocation-free adjoint's scratch (looked up once per device)
+  if (scratch_lookup(c->device) != LBSMRT_OK) { free_ctx(c); return LBSMRT_E_HIP; }
   auto fail = [&](lbsmrt_status code) { free_ctx(c); return code; };
   if (hipMalloc(&c->d_doms, sizeof(DomainDev) * dd.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
   if (hipMalloc(&c->d_blocks, sizeof(BlockDev) * bl.size()) != hipSuccess) return fail(LBSMRT_E_NOMEM);
@@ -539,17 +597,24 @@ lbsmrt_status lbsmrt_equilibrium(lbsmrt_ctx* c, const double* fields, float* f, 
 
 lbsmrt_status lbsmrt_step_adjoint(lbsmrt_ctx* c, const float* f_t, const float* lam_next, float* lam_t,
                                   double* dL_dtau, void* stream) {
-  if (!c || !f_t || !lam_next || !lam_t || !dL_dtau) return LBSMRT_E_ARG;
-  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
-  if (lam_t == lam_next || lam_t == f_t) return LBSMRT_E_ARG;
-  if (c->additive) return LBSMRT_E_UNSUPPORTED;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  StepArgs A = step_args(c);
-  A.blocks = c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj);
-  if (!c->shock && c->n_blocks_adjR > 0) A.blocks = c->d_blocks_adjR;
-  A.dtau = dL_dtau;
-  dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, s); });
-  return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+  const lbsmrt_status st = adjoint_check(c, f_t, lam_next, lam_t, dL_dtau);
+  if (st != LBSMRT_OK) return st;
+  return adjoint_launch(c, f_t, lam_next, lam_t, dL_dtau, c->d_partial, c->d_stage, stream);
+}
+
+lbsmrt_status lbsmrt_step_adjoint_noalloc(lbsmrt_ctx* c, const float* f_t, const float* lam_next, float* lam_t,
+                                          double* dL_dtau, void* stream) {
+  const lbsmrt_status st = adjoint_check(c, f_t, lam_next, lam_t, dL_dtau);
+  if (st != LBSMRT_OK) return st;
+  const size_t cols = static_cast<size_t>(n_tau_slots(c->N));
+  if (cols * (static_cast<size_t>(adjoint_groups(c)) + kReduceBlocks) > kScratchDoubles) return LBSMRT_E_LIMIT;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBSMRT_E_HIP;
+  if (dev != c->device) return LBSMRT_E_ARG;   // the context's device must be current
+  double* base = scratch_address(dev);
+  if (!base) return LBSMRT_E_UNSUPPORTED;   // device ordinal beyond the lookup table
+  // partials first, then the stage rows; every row the reduction reads is written by this call
+  return adjoint_launch(c, f_t, lam_next, lam_t, dL_dtau, base, base + cols * adjoint_groups(c), stream);
 }
 
 lbsmrt_status lbsmrt_loss_seed(lbsmrt_ctx* c, const float* f, const double* target, const double* scales, float* lam,

@@ -149,6 +149,16 @@ class Lattice:
                 "lbsmrt_step_adjoint")
         return lam_t
 
+    def step_adjoint_noalloc(self, f_t, lam_next, lam_t, dL_dtau):
+        """step_adjoint through the allocation-free entry point (library-held scratch, one per GPU;
+        calls that overlap on one GPU race).  LbsmrtError with E_LIMIT beyond its size limit."""
+        C.check(C.lib().lbsmrt_step_adjoint_noalloc(self._h, _dev_ptr(f_t, torch.float32, "f_t"),
+                                                    _dev_ptr(lam_next, torch.float32, "lam_next"),
+                                                    _dev_ptr(lam_t, torch.float32, "lam_t"),
+                                                    _dev_ptr(dL_dtau, torch.float64, "dL_dtau"), _stream_ptr()),
+                "lbsmrt_step_adjoint_noalloc")
+        return lam_t
+
     def loss_seed(self, f, target, scales, lam, loss):
         sc = (ctypes.c_double * 3)(*[float(s) for s in scales])
         C.check(C.lib().lbsmrt_loss_seed(self._h, _dev_ptr(f, torch.float32, "f"),
