@@ -10,7 +10,8 @@ roofline of the step kernel (HBM bound: one FP32 read and one FP32 write of
 every population per node-step = 8 Q bytes; beside the nominal peak, a plain
 device copy of one state buffer measured in the same run), the FP64 CPU oracle
 timed on a bounded sample of the same workload, and variants of the same box:
-the other contraction precision, the additive collision, the moment-state form
+the other contraction forms (FP32 on the vector units, split-BF16x3 on the matrix
+cores, with its bf16 matrix-core flop rate), the additive collision, the moment-state form
 of the step (state held as the M moments), the adjoint step, the Ma 3 D3Q729
 calibration shock and the batched 64-shock Mach sweep.
 """
@@ -25,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of the MI355X
+PRECISIONS = ("fp64_contract", "fp32", "split_bf16x3")
 
 WORKLOADS = {
     # name: (abscissae, degree, N, box edge)
@@ -99,7 +102,7 @@ def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
     fields = torch.tensor(W.fourier_box(sample_edge), dtype=torch.float64, device="cuda")
     gpu = {}
     f32 = None
-    for precision in ("fp64_contract", "fp32"):
+    for precision in PRECISIONS:
         lat = Lattice(ab, deg, N, tau, box, precision=precision)
         fa = lat.equilibrium(fields)
         if f32 is None:
@@ -278,14 +281,18 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     from paper_2401_11086_amd import Lattice
     out = {}
     steps = max(4, args.steps // 2)
-    other = "fp32" if args.precision == "fp64_contract" else "fp64_contract"
-    lat2 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision=other)
-    lat2.step(fa, fb, 2)
-    ms = _time_steps(torch, lambda: lat2.step(fa, fb, 1), steps)
-    lat2.sync()
-    out[other] = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2)}
-    lat2.close()
-    _progress(f"{other}: {ms:.3f} ms/step")
+    for other in [p for p in PRECISIONS if p != args.precision]:
+        lat2 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision=other)
+        lat2.step(fa, fb, 2)
+        ms = _time_steps(torch, lambda: lat2.step(fa, fb, 1), steps)
+        lat2.sync()
+        rec = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2),
+               "hbm_frac": round(8.0 * lat.Q * lat.n_nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if other == "split_bf16x3":
+            rec.update(mfma_record(lat2, ms))
+        out[other] = rec
+        lat2.close()
+        _progress(f"{other}: {ms:.3f} ms/step")
     # additive collision f* = g + R (a' - a): the pulled populations are read twice (12 Q B/node)
     lat3 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision="fp64_contract",
                    regularized=False)
@@ -311,6 +318,39 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
                       "achieved_GBs": round(12.0 * lat.Q * lat.n_nodes / (ms_adj / 1e3) / 1e9, 1)}
     del lam_a, lam_b
     return out
+
+
+CONTRACTION_TEXT = {"fp64_contract": "FP64 folded contractions", "fp32": "FP32 contractions",
+                    "split_bf16x3": "split-BF16x3 matrix-core contractions"}
+
+
+def step_kernel_name(lat, precision):
+    if precision == "split_bf16x3":
+        return f"k_collide_stream_bf16x3<{lat.Q1},{lat.N},false>"
+    return f"k_collide_stream<{lat.Q1},{lat.N},false,{2 if precision == 'fp64_contract' else 0},1,false>"
+
+
+def mfma_flops(lat):
+    """Matrix-core flops per node-step of the split-BF16x3 form, three bf16 products each:
+    algorithmic (projection of the orders 2..N, (M - 4) x Q, and the rebuild with its five
+    correction columns, Q x (M + 5)) and issued (the same contractions padded to the 32 x 32 x 16
+    tiles of v_mfma_f32_32x32x16_bf16: 32-row tiles of projected moments over ceil(Q1 / 2) or 6
+    k-steps per x-slab, 32-row tiles of populations over 16-wide steps of the rebuild k axis)."""
+    Q1, Q, M = lat.Q1, lat.Q, lat.M
+    algorithmic = 2 * 3 * ((M - 4) * Q + Q * (M + 5))
+    kpx = (Q1 + 1) // 2 if Q1 <= 8 else 6
+    issued = 2 * 3 * (32 * math.ceil((M - 4) / 32) * Q1 * kpx * 16
+                      + 32 * math.ceil(Q / 32) * 16 * math.ceil((M + 5) / 16))
+    return algorithmic, issued
+
+
+def mfma_record(lat, ms):
+    alg, issued = mfma_flops(lat)
+    n = lat.n_nodes
+    return {"mfma_flops_per_node": alg, "mfma_issued_flops_per_node": issued,
+            "mfma_TFLOPs": round(alg * n / (ms / 1e3) / 1e12, 1),
+            "mfma_issued_TFLOPs": round(issued * n / (ms / 1e3) / 1e12, 1),
+            "mfma_frac_of_bf16_peak": round(issued * n / (ms / 1e3) / 1e12 / MFMA_BF16_PEAK_TFLOPS, 4)}
 
 
 def moment_state_bytes(lat):
@@ -471,7 +511,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="box256_q343_n4", choices=sorted(WORKLOADS))
     ap.add_argument("--kn", type=float, default=0.05)
-    ap.add_argument("--precision", default="fp64_contract", choices=["fp32", "fp64_contract"])
+    ap.add_argument("--precision", default="fp64_contract", choices=list(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched Mach sweep")
     ap.add_argument("--batched-steps", type=int, default=5000)
@@ -552,20 +592,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        # arithmetic type of the path (the state is stored in FP32 in both precisions)
-        "dtype": "f64" if args.precision == "fp64_contract" else "f32",
+        # arithmetic type of the contractions (the state is stored in FP32 in every form)
+        "dtype": {"fp64_contract": "f64", "fp32": "f32", "split_bf16x3": "bf16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{edge}^3 periodic box, D3Q{lat.Q} (D1Q{lat.Q1} degree {deg}), Hermite N={N}, "
                                f"Kn={args.kn}, 16 Fourier modes per field, FP32 state, "
-                               + ("FP64 folded contractions" if args.precision == "fp64_contract"
-                                  else "FP32 contractions") + ", FP64 moment section",
+                               + CONTRACTION_TEXT[args.precision] + ", FP64 moment section",
                    "nodes": nodes, "Q": lat.Q, "M": lat.M, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(args.workload, args.precision),
-                     "kernel": f"k_collide_stream<{lat.Q1},{N},false,{2 if args.precision == 'fp64_contract' else 0},1,false>",
+                     "kernel": step_kernel_name(lat, args.precision),
                      "bytes_per_launch": bytes_per_launch},
     }
+    if args.precision == "split_bf16x3":
+        # the matrix-core roofline of the same launch (algorithmic bf16 flops)
+        mf = mfma_record(lat, ms_step)
+        out["roofline_mfma"] = {"bound": "mfma", "achieved": mf["mfma_TFLOPs"], "peak": MFMA_BF16_PEAK_TFLOPS,
+                                "unit": "TFLOP/s", "frac": round(mf["mfma_TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, 4),
+                                **mf}
     if variants:
         out["variants"] = variants
     # measured streaming ceiling on the same buffers (a plain copy, read + write)
