@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int KPX = S::KPX;
   constexpr int AT = S::ATILES;
   constexpr int KR = S::KSTEPS_R;
-  constexpr int kFence = Q1 <= 8 ? 2 : 1;   // k-steps per group of loads
+  constexpr int kFence = Q1 <= 8 ? 4 : 2;   // k-steps per group of loads
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int j = lane & 31;
   const int h = lane >> 5;
@@ -170,95 +170,123 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int i = 0; i < Q1; ++i) asm volatile("" : "+s"(yo[t][i]), "+s"(zo[t][i]));
+    // Groups of kFence k-steps: every load of the group is issued first, then the values are
+    // consumed in order (the scheduling barrier keeps the consumers behind the loads, so one
+    // memory round trip serves the whole group instead of one load after another).
 #pragma unroll
-    for (int p = 0; p < KPX; ++p) {
-      const int s = ix * KPX + p;
-      // the population of element e for either half-wave (compile-time candidates, selected per
-      // lane by h); when every element of a half-wave lies on one z line the conserved sums are
-      // taken per line, else per element
-      const bool lines = Q1 <= 8 || p < 4;
-      bf16x8_t bh[2], bl[2];
+    for (int p0 = 0; p0 < KPX; p0 += kFence) {
+      float gv[kFence][2][8];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        float g[8];
-        double V0 = 0.0, V1 = 0.0, V2 = 0.0;
-        double Se[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int pp = 0; pp < kFence; ++pp) {
+        const int p = p0 + pp;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          // (iy, iz) depend only on the k-step p inside the slab: evaluated at compile time
-          int ixA = 0, iyA = 0, izA = 0, ixB = 0, iyB = 0, izB = 0;
-          const bool okA = proj_pop(Q1, p, 0, e, ixA, iyA, izA);
-          const bool okB = proj_pop(Q1, p, 1, e, ixB, iyB, izB);
-          float v = 0.f;
-          if (h == 0 ? okA : okB) {
-            const int iyAc = okA ? iyA : 0, izAc = okA ? izA : 0, iyBc = okB ? iyB : 0, izBc = okB ? izB : 0;
-            // population inside the slab and its y/z source offset, for either half-wave
-            const int qsA = iyAc * Q1 + izAc, qsB = iyBc * Q1 + izBc;
-            const unsigned oA = yo[t][iyAc] + zo[t][izAc] + static_cast<unsigned>(qsA) * sb;
-            const unsigned oB = yo[t][iyBc] + zo[t][izBc] + static_cast<unsigned>(qsB) * sb;
-            v = load_at(fx, tp[t].xoff + oA + (hmask & (oB - oA)));
-            if (SHOCK && tp[t].any_ghost) {
-              const int qs = h == 0 ? qsA : qsB;
-              const float gv = A.ghosts[static_cast<size_t>(ix * Q1 * Q1 + qs) * A.n_ghost + D.ghost + tp[t].gside];
-              v = tp[t].ghost ? gv : v;
-            }
-            const double vd = static_cast<double>(v);
-            constexpr auto& kE = MfmaStencil<Q1>::e;
-            const int hm = static_cast<int>(hmask);
-            const double ez = static_cast<double>(kE[izAc] + (hm & (kE[izBc] - kE[izAc])));
-            if (lines) {
-              const int zA2 = kE[izAc] * kE[izAc], zB2 = kE[izBc] * kE[izBc];
-              const double ez2 = static_cast<double>(zA2 + (hm & (zB2 - zA2)));
-              V0 += vd;
-              V1 = fma(vd, ez, V1);
-              V2 = fma(vd, ez2, V2);
-            } else {
-              const double ey = static_cast<double>(kE[iyAc] + (hm & (kE[iyBc] - kE[iyAc])));
-              const int sA = kE[iyAc] * kE[iyAc] + kE[izAc] * kE[izAc], sB = kE[iyBc] * kE[iyBc] + kE[izBc] * kE[izBc];
-              const double e2 = static_cast<double>(sA + (hm & (sB - sA)));
-              Se[0] += vd;
-              Se[2] = fma(vd, ey, Se[2]);
-              Se[3] = fma(vd, ez, Se[3]);
-              Se[4] = fma(vd, e2, Se[4]);
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            int ixA = 0, iyA = 0, izA = 0, ixB = 0, iyB = 0, izB = 0;
+            const bool okA = p < KPX && proj_pop(Q1, p, 0, e, ixA, iyA, izA);
+            const bool okB = p < KPX && proj_pop(Q1, p, 1, e, ixB, iyB, izB);
+            gv[pp][t][e] = 0.f;
+            if (okA || okB) {
+              // where only one half-wave has a population here (okA, okB are compile-time), the
+              // other loads the same address and zeroes the value below: no load sits in a
+              // lane-divergent branch, where it would wait for its own return
+              const int iyAc = okA ? iyA : iyB, izAc = okA ? izA : izB;
+              const int iyBc = okB ? iyB : iyAc, izBc = okB ? izB : izAc;
+              const unsigned oA = yo[t][iyAc] + zo[t][izAc] + static_cast<unsigned>(iyAc * Q1 + izAc) * sb;
+              const unsigned oB = yo[t][iyBc] + zo[t][izBc] + static_cast<unsigned>(iyBc * Q1 + izBc) * sb;
+              gv[pp][t][e] = load_at(fx, tp[t].xoff + oA + (hmask & (oB - oA)));
             }
           }
-          g[e] = v;
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const __bf16 hi = static_cast<__bf16>(g[e]);
-          bh[t][e] = hi;
-          bl[t][e] = static_cast<__bf16>(g[e] - static_cast<float>(hi));
-        }
-        const double exd = static_cast<double>(ex);
-        if (lines) {   // the half-wave's line (ix, iy): fold its sums with e_x and e_y
-          int i0 = 0, yA = 0, z0 = 0, yB = 0;
-          proj_pop(Q1, p, 0, 0, i0, yA, z0);
-          proj_pop(Q1, p, 1, 0, i0, yB, z0);
-          constexpr auto& kE = MfmaStencil<Q1>::e;
-          const int eyA = kE[yA < Q1 ? yA : 0], eyB = kE[yB < Q1 ? yB : 0];
-          const double ey = static_cast<double>(eyA + (static_cast<int>(hmask) & (eyB - eyA)));
-          Sg[t][0] += V0;
-          Sg[t][1] = fma(V0, exd, Sg[t][1]);
-          Sg[t][2] = fma(V0, ey, Sg[t][2]);
-          Sg[t][3] += V1;
-          Sg[t][4] = fma(V0, exd * exd + ey * ey, Sg[t][4] + V2);
-        } else {
-          Sg[t][0] += Se[0];
-          Sg[t][1] = fma(Se[0], exd, Sg[t][1]);
-          Sg[t][2] += Se[2];
-          Sg[t][3] += Se[3];
-          Sg[t][4] = fma(Se[0], exd * exd, Sg[t][4] + Se[4]);
-        }
       }
-      // keep at most kFence k-steps of loads in flight (registers for two waves per SIMD)
-      if ((p + 1) % kFence == 0) asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int a = 0; a < AT; ++a) {
-        const bf16x8_t ah = as_bf16x8(T.proj[(static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane]);
-        const bf16x8_t al = as_bf16x8(T.proj[S::PROJ_VEC + (static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane]);
+      for (int pp = 0; pp < kFence; ++pp) {
+        const int p = p0 + pp;
+        if (p >= KPX) break;
+        const int s = ix * KPX + p;
+        // when every element of a half-wave lies on one z line the conserved sums are taken per
+        // line, else per element
+        const bool lines = Q1 <= 8 || p < 4;
+        bf16x8_t bh[2], bl[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[a][t] = mfma3(ah, al, bh[t], bl[t], acc[a][t]);
+        for (int t = 0; t < 2; ++t) {
+          float g[8];
+          double V0 = 0.0, V1 = 0.0, V2 = 0.0;
+          double Se[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            // (iy, iz) depend only on the k-step p inside the slab: evaluated at compile time
+            int ixA = 0, iyA = 0, izA = 0, ixB = 0, iyB = 0, izB = 0;
+            const bool okA = proj_pop(Q1, p, 0, e, ixA, iyA, izA);
+            const bool okB = proj_pop(Q1, p, 1, e, ixB, iyB, izB);
+            float v = 0.f;
+            if (okA || okB) {
+              const int iyAc = okA ? iyA : iyB, izAc = okA ? izA : izB;
+              const int iyBc = okB ? iyB : iyAc, izBc = okB ? izB : izAc;
+              v = gv[pp][t][e];
+              if (SHOCK && tp[t].any_ghost) {
+                const int qs = h == 0 ? iyAc * Q1 + izAc : iyBc * Q1 + izBc;
+                const float gh = A.ghosts[static_cast<size_t>(ix * Q1 * Q1 + qs) * A.n_ghost + D.ghost + tp[t].gside];
+                v = tp[t].ghost ? gh : v;
+              }
+              if (!(okA && okB)) v = (okA ? h == 0 : h != 0) ? v : 0.f;
+              const double vd = static_cast<double>(v);
+              constexpr auto& kE = MfmaStencil<Q1>::e;
+              const int hm = static_cast<int>(hmask);
+              const double ez = static_cast<double>(kE[izAc] + (hm & (kE[izBc] - kE[izAc])));
+              if (lines) {
+                const int zA2 = kE[izAc] * kE[izAc], zB2 = kE[izBc] * kE[izBc];
+                const double ez2 = static_cast<double>(zA2 + (hm & (zB2 - zA2)));
+                V0 += vd;
+                V1 = fma(vd, ez, V1);
+                V2 = fma(vd, ez2, V2);
+              } else {
+                const double ey = static_cast<double>(kE[iyAc] + (hm & (kE[iyBc] - kE[iyAc])));
+                const int sA = kE[iyAc] * kE[iyAc] + kE[izAc] * kE[izAc], sB = kE[iyBc] * kE[iyBc] + kE[izBc] * kE[izBc];
+                const double e2 = static_cast<double>(sA + (hm & (sB - sA)));
+                Se[0] += vd;
+                Se[2] = fma(vd, ey, Se[2]);
+                Se[3] = fma(vd, ez, Se[3]);
+                Se[4] = fma(vd, e2, Se[4]);
+              }
+            }
+            g[e] = v;
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const __bf16 hi = static_cast<__bf16>(g[e]);
+            bh[t][e] = hi;
+            bl[t][e] = static_cast<__bf16>(g[e] - static_cast<float>(hi));
+          }
+          const double exd = static_cast<double>(ex);
+          if (lines) {   // the half-wave's line (ix, iy): fold its sums with e_x and e_y
+            int i0 = 0, yA = 0, z0 = 0, yB = 0;
+            proj_pop(Q1, p, 0, 0, i0, yA, z0);
+            proj_pop(Q1, p, 1, 0, i0, yB, z0);
+            constexpr auto& kE = MfmaStencil<Q1>::e;
+            const int eyA = kE[yA < Q1 ? yA : 0], eyB = kE[yB < Q1 ? yB : 0];
+            const double ey = static_cast<double>(eyA + (static_cast<int>(hmask) & (eyB - eyA)));
+            Sg[t][0] += V0;
+            Sg[t][1] = fma(V0, exd, Sg[t][1]);
+            Sg[t][2] = fma(V0, ey, Sg[t][2]);
+            Sg[t][3] += V1;
+            Sg[t][4] = fma(V0, exd * exd + ey * ey, Sg[t][4] + V2);
+          } else {
+            Sg[t][0] += Se[0];
+            Sg[t][1] = fma(Se[0], exd, Sg[t][1]);
+            Sg[t][2] += Se[2];
+            Sg[t][3] += Se[3];
+            Sg[t][4] = fma(Se[0], exd * exd, Sg[t][4] + Se[4]);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < AT; ++a) {
+          const bf16x8_t ah = as_bf16x8(T.proj[(static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane]);
+          const bf16x8_t al = as_bf16x8(T.proj[S::PROJ_VEC + (static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane]);
+#pragma unroll
+          for (int t = 0; t < 2; ++t) acc[a][t] = mfma3(ah, al, bh[t], bl[t], acc[a][t]);
+        }
       }
     }
   }
@@ -401,47 +429,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // value, runs from a zero accumulator; every other product (higher orders, then the lo
   // halves and the correction columns) runs in a second chain of smaller values; one
   // round-to-nearest add per population joins them.
+  // The tables of q-tile tau are loaded while tile tau - 1 is processed, ahead of its stores:
+  // stores and loads share one counter, so a table load issued after a tile's stores would make
+  // the next tile wait for all of them.  Only the last tile has rows past Q; the stores of a
+  // tile share one validity test (a whole tile is past the end of a periodic domain, or not).
   const unsigned hoff = static_cast<unsigned>(h) * 4u * sbytes + static_cast<unsigned>(j) * 4u;
-#pragma unroll 1
+  u32x4_t th[KR], tl[KR];
+#pragma unroll
+  for (int kk = 0; kk < KR; ++kk) {
+    th[kk] = T.rebuild[kk * 64 + lane];
+    tl[kk] = T.rebuild[S::REB_VEC + kk * 64 + lane];
+  }
+#pragma unroll
   for (int tau = 0; tau < S::QTILES; ++tau) {
-    const long long at0 = static_cast<long long>(tau) * KR * 64 + lane;
-    f32x16_t big0, big1, c0 = f32x16_t{}, c1 = f32x16_t{};
-    {
-      const bf16x8_t th = as_bf16x8(T.rebuild[at0]);
-      big0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, B1[0][0], f32x16_t{}, 0, 0, 0);
-      big1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, B1[1][0], f32x16_t{}, 0, 0, 0);
+    const int tn = tau + 1 < S::QTILES ? tau + 1 : tau;
+    const long long an = static_cast<long long>(tn) * KR * 64 + lane;
+    u32x4_t nh[KR], nl[KR];
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      nh[kk] = T.rebuild[an + kk * 64];
+      nl[kk] = T.rebuild[S::REB_VEC + an + kk * 64];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    f32x16_t big0, big1, c0 = f32x16_t{}, c1 = f32x16_t{};
+    big0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(th[0]), B1[0][0], f32x16_t{}, 0, 0, 0);
+    big1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(th[0]), B1[1][0], f32x16_t{}, 0, 0, 0);
 #pragma unroll
     for (int kk = KR - 1; kk >= 1; --kk) {
-      const bf16x8_t th = as_bf16x8(T.rebuild[at0 + kk * 64]);
-      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, B1[0][kk], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, B1[1][kk], c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(th[kk]), B1[0][kk], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(th[kk]), B1[1][kk], c1, 0, 0, 0);
     }
 #pragma unroll
     for (int kk = KR - 1; kk >= 0; --kk) {
-      const bf16x8_t th = as_bf16x8(T.rebuild[at0 + kk * 64]);
-      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, B2[0][kk], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(th, B2[1][kk], c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(th[kk]), B2[0][kk], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(th[kk]), B2[1][kk], c1, 0, 0, 0);
     }
 #pragma unroll
     for (int kk = KR - 1; kk >= 0; --kk) {
-      const bf16x8_t tl = as_bf16x8(T.rebuild[S::REB_VEC + at0 + kk * 64]);
-      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tl, B1[0][kk], c0, 0, 0, 0);
-      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(tl, B1[1][kk], c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(tl[kk]), B1[0][kk], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(tl[kk]), B1[1][kk], c1, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       c0[v] = big0[v] + c0[v];
       c1[v] = big1[v] + c1[v];
     }
+    float* __restrict__ base0 = fdst + static_cast<size_t>(32 * tau) * A.stride + D.off + tstart[0];
+    float* __restrict__ base1 = fdst + static_cast<size_t>(32 * tau) * A.stride + D.off + tstart[1];
+    if (tau + 1 < S::QTILES) {
+      if (valid[0]) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int q0 = 32 * tau + 8 * (v / 4) + (v % 4);   // population of the lower half-wave
-      const bool qok = q0 + 4 * h < S::Q;
-      float* __restrict__ base0 = fdst + static_cast<size_t>(q0) * A.stride + D.off + tstart[0];
-      float* __restrict__ base1 = fdst + static_cast<size_t>(q0) * A.stride + D.off + tstart[1];
-      if (qok && valid[0]) store_pop<!SHOCK>(base0, hoff, c0[v]);
-      if (qok && valid[1]) store_pop<!SHOCK>(base1, hoff, c1[v]);
+        for (int v = 0; v < 16; ++v)
+          store_pop<!SHOCK>(base0 + static_cast<size_t>(8 * (v / 4) + (v % 4)) * A.stride, hoff, c0[v]);
+      }
+      if (valid[1]) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          store_pop<!SHOCK>(base1 + static_cast<size_t>(8 * (v / 4) + (v % 4)) * A.stride, hoff, c1[v]);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = 8 * (v / 4) + (v % 4);   // row of the lower half-wave in the tile
+        const bool qok = 32 * tau + r + 4 * h < S::Q;
+        if (qok && valid[0]) store_pop<!SHOCK>(base0 + static_cast<size_t>(r) * A.stride, hoff, c0[v]);
+        if (qok && valid[1]) store_pop<!SHOCK>(base1 + static_cast<size_t>(r) * A.stride, hoff, c1[v]);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      th[kk] = nh[kk];
+      tl[kk] = nl[kk];
     }
   }
 }
