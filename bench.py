@@ -420,10 +420,16 @@ def time_shock_adjoint(torch, steps=300):
     lat.sync()
     assert torch.isfinite(dtau).all()
     lat.close()
-    _progress(f"shock adjoint (Nx 600, D3Q729): forward {ms_fwd * 1e3:.1f} us (moment state {ms_mom * 1e3:.1f} us), "
-              f"adjoint {ms_adj * 1e3:.1f} us")
+    lat_b = Lattice(ab, deg, N, tau, [d], shift_k=(2, 0, 0), precision="split_bf16x3")
+    ga, gb = lat_b.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda")), lat_b.new_state()
+    lat_b.step(ga, gb, 10)
+    ms_b = _time_steps(torch, lambda: lat_b.step(ga, gb, 1), steps)
+    lat_b.sync()
+    lat_b.close()
+    _progress(f"shock adjoint (Nx 600, D3Q729): forward {ms_fwd * 1e3:.1f} us (moment state {ms_mom * 1e3:.1f} us, "
+              f"split-BF16x3 {ms_b * 1e3:.1f} us), adjoint {ms_adj * 1e3:.1f} us")
     return {"workload": "Ma 3 shock, Nx 600, D3Q729, N=5, FP64 contractions", "forward_us": round(ms_fwd * 1e3, 2),
-            "forward_moment_state_us": round(ms_mom * 1e3, 2),
+            "forward_moment_state_us": round(ms_mom * 1e3, 2), "forward_split_bf16x3_us": round(ms_b * 1e3, 2),
             "adjoint_us": round(ms_adj * 1e3, 2), "ratio_to_forward": round(ms_adj / ms_fwd, 3)}
 
 
@@ -477,6 +483,20 @@ def time_batched(torch, n_shocks=64, steps=5000, seed=0):
                                    "speedup_vs_population_batch": round(ms / ms_m, 2)}
     _progress(f"batched sweep, moment state: {ms_m * 1e3:.1f} us/step")
     del ma, mb
+    # the same batch with the split-BF16x3 matrix-core contractions (one launch per step)
+    lat_b = Lattice(ab, deg, N, tau, doms, shift_k=(2, 0, 0), precision="split_bf16x3")
+    ga, gb = lat_b.equilibrium(fl), lat_b.new_state()
+    lat_b.step(ga, gb, 2)
+    lat_b.sync()
+    ms_b = _time_steps(torch, lambda: lat_b.step(ga, gb, steps), 1) / steps
+    lat_b.sync()
+    out["batched_split_bf16x3"] = {"ms_per_step": round(ms_b, 5), "mlups": round(nodes / (ms_b / 1e3) / 1e6, 1),
+                                   "achieved_GBs": round(8.0 * lat.Q * nodes / (ms_b / 1e3) / 1e9, 1),
+                                   "speedup_vs_population_batch": round(ms / ms_b, 3),
+                                   **mfma_record(lat_b, ms_b)}
+    _progress(f"batched sweep, split-BF16x3: {ms_b * 1e3:.1f} us/step")
+    lat_b.close()
+    del ga, gb
     # the same shocks as separate contexts, one launch per shock per step
     sep = []
     for d, f in zip(doms, fields):

@@ -53,14 +53,6 @@ __device__ __forceinline__ void swap_halves(double& a, double& b) {
 __device__ __forceinline__ bf16x8_t as_bf16x8(const u32x4_t& v) { return __builtin_bit_cast(bf16x8_t, v); }
 __device__ __forceinline__ u32x4_t as_u32x4(const bf16x8_t& v) { return __builtin_bit_cast(u32x4_t, v); }
 
-__device__ __forceinline__ f32x16_t mfma3(const bf16x8_t& ah, const bf16x8_t& al, const bf16x8_t& bh,
-                                          const bf16x8_t& bl, f32x16_t c) {
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
-  return c;
-}
-
 // One node tile of the gather: where a lane's node pulls from in the current x-slab.
 struct TilePull {
   unsigned xoff;   // byte offset of (domain start + source x), before the y/z and plane offsets
@@ -79,6 +71,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   constexpr int AT = S::ATILES;
   constexpr int KR = S::KSTEPS_R;
   constexpr int kFence = Q1 <= 8 ? 4 : 2;   // k-steps per group of loads
+  constexpr bool kProjAhead = Q1 <= 8;
+  constexpr bool kRebLds = Q1 <= 8;   // both rebuild-table halves fit in LDS (66 KB at N = 4)
+  __shared__ u32x4_t reb_lds[kRebLds ? 2 * S::REB_VEC : 1];
+  if constexpr (kRebLds) {
+    constexpr int kPer = static_cast<int>((2 * S::REB_VEC + 255) / 256);
+    u32x4_t tmp[kPer];   // every load in flight before the first LDS write
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = static_cast<int>(threadIdx.x) + 256 * k;
+      if (i < 2 * S::REB_VEC) tmp[k] = T.rebuild[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = static_cast<int>(threadIdx.x) + 256 * k;
+      if (i < 2 * S::REB_VEC) reb_lds[i] = tmp[k];
+    }
+    __syncthreads();
+  }
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int j = lane & 31;
   const int h = lane >> 5;
@@ -123,9 +133,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 
   // ---------------------------------------------------------------- gather + projection
-  // Each x-slab's products accumulate on the matrix cores from zero; the slab sums are added on
-  // the vector ALU (round to nearest), so the low bits the matrix cores drop stay relative to one
-  // slab's sum instead of compounding over the whole contraction.
   f32x16_t acc[AT][2];
 #pragma unroll
   for (int a = 0; a < AT; ++a)
@@ -198,6 +205,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
               gv[pp][t][e] = load_at(fx, tp[t].xoff + oA + (hmask & (oB - oA)));
             }
           }
+      }
+      // the projection-table operands of the group's k-steps travel with the same round trip
+      // (7-point stencil; with 9 points the registers they need would spill)
+      u32x4_t pa[kFence][AT][2];
+#pragma unroll
+      for (int pp = 0; pp < (kProjAhead ? kFence : 0); ++pp) {
+        const int s = ix * KPX + (p0 + pp < KPX ? p0 + pp : KPX - 1);
+#pragma unroll
+        for (int a = 0; a < AT; ++a) {
+          pa[pp][a][0] = T.proj[(static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane];
+          pa[pp][a][1] = T.proj[S::PROJ_VEC + (static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane];
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -282,10 +301,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
 #pragma unroll
         for (int a = 0; a < AT; ++a) {
-          const bf16x8_t ah = as_bf16x8(T.proj[(static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane]);
-          const bf16x8_t al = as_bf16x8(T.proj[S::PROJ_VEC + (static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane]);
+          const long long ta = (static_cast<long long>(a) * S::KSTEPS_P + s) * 64 + lane;
+          const bf16x8_t ah = as_bf16x8(kProjAhead ? pa[pp][a][0] : T.proj[ta]);
+          const bf16x8_t al = as_bf16x8(kProjAhead ? pa[pp][a][1] : T.proj[S::PROJ_VEC + ta]);
 #pragma unroll
-          for (int t = 0; t < 2; ++t) acc[a][t] = mfma3(ah, al, bh[t], bl[t], acc[a][t]);
+          for (int t = 0; t < 2; ++t) {
+            acc[a][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[t], acc[a][t], 0, 0, 0);
+            acc[a][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[t], acc[a][t], 0, 0, 0);
+            acc[a][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[t], acc[a][t], 0, 0, 0);
+          }
         }
       }
     }
@@ -429,16 +453,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // value, runs from a zero accumulator; every other product (higher orders, then the lo
   // halves and the correction columns) runs in a second chain of smaller values; one
   // round-to-nearest add per population joins them.
-  // The tables of q-tile tau are loaded while tile tau - 1 is processed, ahead of its stores:
-  // stores and loads share one counter, so a table load issued after a tile's stores would make
-  // the next tile wait for all of them.  Only the last tile has rows past Q; the stores of a
-  // tile share one validity test (a whole tile is past the end of a periodic domain, or not).
+  // Rebuild tables: with the 7-point stencil both halves sit in LDS (copied there at the start of
+  // the work-group), so their reads wait on the LDS counter alone.  Otherwise the tables of q-tile
+  // tau are loaded from memory while tile tau - 1 is processed; global loads and stores share one
+  // counter, so each tile still waits for the previous tile's stores.  Only the last tile has rows
+  // past Q; the stores of a tile share one validity test (a whole tile is past the end of a
+  // periodic domain, or not).
   const unsigned hoff = static_cast<unsigned>(h) * 4u * sbytes + static_cast<unsigned>(j) * 4u;
+  const u32x4_t* __restrict__ rtab = T.rebuild;
+  if constexpr (kRebLds) rtab = reb_lds;
   u32x4_t th[KR], tl[KR];
 #pragma unroll
   for (int kk = 0; kk < KR; ++kk) {
-    th[kk] = T.rebuild[kk * 64 + lane];
-    tl[kk] = T.rebuild[S::REB_VEC + kk * 64 + lane];
+    th[kk] = rtab[kk * 64 + lane];
+    tl[kk] = rtab[S::REB_VEC + kk * 64 + lane];
   }
 #pragma unroll
   for (int tau = 0; tau < S::QTILES; ++tau) {
@@ -447,8 +475,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     u32x4_t nh[KR], nl[KR];
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) {
-      nh[kk] = T.rebuild[an + kk * 64];
-      nl[kk] = T.rebuild[S::REB_VEC + an + kk * 64];
+      nh[kk] = rtab[an + kk * 64];
+      nl[kk] = rtab[S::REB_VEC + an + kk * 64];
     }
     __builtin_amdgcn_sched_barrier(0);
     f32x16_t big0, big1, c0 = f32x16_t{}, c1 = f32x16_t{};
