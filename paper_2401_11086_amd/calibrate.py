@@ -55,6 +55,35 @@ def loss_only(fit, tau):
     return fit.forward()
 
 
+def descend(fit, tau, iters, L0=None, g0=None, log=None):
+    """Gradient descent on log tau with Armijo backtracking (step doubled after each accepted
+    step, halved while the sufficient-decrease test fails): returns the final times and the
+    misfit after every iteration (history[0] is the start)."""
+    keys = fit.keys
+    if L0 is None or g0 is None:
+        L0, g0 = loss_grad(fit, tau)
+    hist = [L0]
+    L, g = L0, g0
+    logt = {k: math.log(tau[k]) for k in keys}
+    eta = 0.05 / max(abs(g[k] * tau[k]) for k in keys)
+    for it in range(iters):
+        gl = {k: g[k] * math.exp(logt[k]) for k in keys}
+        gn2 = sum(v * v for v in gl.values())
+        while True:
+            trial = {k: logt[k] - eta * gl[k] for k in keys}
+            Lt = loss_only(fit, {k: math.exp(v) for k, v in trial.items()})
+            if Lt <= L - 1e-4 * eta * gn2 or eta < 1e-12:
+                break
+            eta *= 0.5
+        logt = trial
+        L, g = loss_grad(fit, {k: math.exp(v) for k, v in logt.items()})
+        hist.append(L)
+        eta *= 2.0
+        if log is not None:
+            log(it + 1, L)
+    return {k: math.exp(v) for k, v in logt.items()}, hist
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--nx", type=int, default=600)
@@ -83,26 +112,9 @@ def main():
     gmax = max(abs(v) for v in g0.values())
     fd_err = {f"{n}{m}": abs(g0[(n, m)] - fd[(n, m)]) / gmax for (n, m) in keys}
     print(f"L0 = {L0:.6e}, adjoint vs FD max rel err {max(fd_err.values()):.2e}", file=sys.stderr, flush=True)
-    # gradient descent on log tau with Armijo backtracking
-    hist = [L0]
-    L, g = L0, g0
-    logt = {k: math.log(tau[k]) for k in keys}
-    eta = 0.05 / max(abs(g[k] * tau[k]) for k in keys)
-    for it in range(args.iters):
-        gl = {k: g[k] * math.exp(logt[k]) for k in keys}
-        gn2 = sum(v * v for v in gl.values())
-        while True:
-            trial = {k: logt[k] - eta * gl[k] for k in keys}
-            Lt = loss_only(fit, {k: math.exp(v) for k, v in trial.items()})
-            if Lt <= L - 1e-4 * eta * gn2 or eta < 1e-12:
-                break
-            eta *= 0.5
-        logt = trial
-        L, g = loss_grad(fit, {k: math.exp(v) for k, v in logt.items()})
-        hist.append(L)
-        eta *= 2.0
-        print(f"iter {it + 1}: L = {L:.6e}", file=sys.stderr, flush=True)
-    tau_fit = {k: math.exp(v) for k, v in logt.items()}
+    tau_fit, hist = descend(fit, tau, args.iters, L0, g0,
+                            log=lambda it, L: print(f"iter {it}: L = {L:.6e}", file=sys.stderr, flush=True))
+    L = hist[-1]
     rel = {f"{n}{m}": (tau_fit[(n, m)] - tau_true[(n, m)]) / tau_true[(n, m)] for (n, m) in keys}
     rel0 = {f"{n}{m}": (tau0[(n, m)] - tau_true[(n, m)]) / tau_true[(n, m)] for (n, m) in keys}
     out = dict(workload=f"Ma=3 shock, Nx={args.nx}, D3Q729, N=5, {args.steps} steps, checkpoints every {args.every}",

@@ -138,3 +138,21 @@ def shift_profile(y, dx):
     """y(x + dx) by linear interpolation (ends held)."""
     x = np.arange(len(y), dtype=float)
     return np.interp(x + dx, x, y)
+
+
+def pull_indices(model, dims, nodes):
+    """Global source node of every population of the given nodes of one periodic box:
+    (Q, n) int64.  dims = (nx, ny, nz)."""
+    nx, ny, nz = dims
+    x, y, z = nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)
+    s = model.streaming_offsets()                        # (Q, 3)
+    xs = (x[None, :] - s[:, 0:1]) % nx
+    ys = (y[None, :] - s[:, 1:2]) % ny
+    zs = (z[None, :] - s[:, 2:3]) % nz
+    return xs + nx * (ys + ny * zs)
+
+
+def gather_columns(torch, f, idx):
+    """f[q, idx[q, j]] for all q, j of a device state -> numpy float64 (Q, n)."""
+    t = torch.tensor(idx, device="cuda")
+    return torch.gather(f[:, :int(idx.max()) + 1], 1, t).double().cpu().numpy()

@@ -9,6 +9,8 @@ import pytest
 import oracle as O
 from paper_2401_11086_amd import workloads as W
 
+from cases import gather_columns, pull_indices
+
 pytestmark = pytest.mark.gpu
 
 TAU_STAR = {k: float(v) for k, v in O.TAU_STAR_SMRT.items()}
@@ -21,24 +23,6 @@ def torch():
     if not t.cuda.is_available():
         pytest.skip("no GPU")
     return t
-
-
-def _pull_indices(model, dims, nodes):
-    """Global source node of every population of the given nodes of one periodic box:
-    (Q, n) int64.  dims = (nx, ny, nz)."""
-    nx, ny, nz = dims
-    x, y, z = nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)
-    s = model.streaming_offsets()                        # (Q, 3)
-    xs = (x[None, :] - s[:, 0:1]) % nx
-    ys = (y[None, :] - s[:, 1:2]) % ny
-    zs = (z[None, :] - s[:, 2:3]) % nz
-    return xs + nx * (ys + ny * zs)
-
-
-def _gather(torch, f, idx):
-    """f[q, idx[q, j]] for all q, j -> numpy float64 (Q, n)."""
-    t = torch.tensor(idx, device="cuda")
-    return torch.gather(f[:, :int(idx.max()) + 1], 1, t).double().cpu().numpy()
 
 
 @pytest.fixture(scope="module")
@@ -67,8 +51,8 @@ def test_box256_step_at_sampled_nodes_matches_oracle(torch, box256):
     lat.sync()
     rng = np.random.default_rng(7)
     nodes = rng.integers(0, lat.n_nodes, size=256)
-    idx = _pull_indices(model, (256, 256, 256), nodes)
-    g = _gather(torch, f0, idx)
+    idx = pull_indices(model, (256, 256, 256), nodes)
+    g = gather_columns(torch, f0, idx)
     ref = O.collide(g, model)
     got = f1[:, torch.tensor(nodes, device="cuda")].double().cpu().numpy()
     err = np.abs(got - ref).max() / np.abs(ref).max()
@@ -98,8 +82,8 @@ def test_box256_adjoint_localised_dot_product(torch, box256):
     s = model.streaming_offsets()
     x0, yy, zz = y0 % 256, (y0 // 256) % 256, y0 // 65536
     tx = ((x0 + s[:, 0]) % 256) + 256 * (((yy + s[:, 1]) % 256) + 256 * ((zz + s[:, 2]) % 256))
-    idx = _pull_indices(model, (256, 256, 256), tx)
-    gx = _gather(torch, f0, idx)                      # (Q, Q): pulled populations of each target node
+    idx = pull_indices(model, (256, 256, 256), tx)
+    gx = gather_columns(torch, f0, idx)                      # (Q, Q): pulled populations of each target node
     pert = np.zeros_like(gx, dtype=complex)
     pert[np.arange(lat.Q), np.arange(lat.Q)] = 1j * H_CS * v    # node i gets v_i on population i
     jv = O.collide(gx + pert, model).imag / H_CS
@@ -144,7 +128,7 @@ def test_mach_sweep_step_at_sampled_nodes_matches_oracle(torch):
         sx = model.streaming_offsets()[:, 0]
         src = xs[None, :] - sx[:, None]                  # (Q, n) x of the source
         inside = (src >= 0) & (src < nx)
-        g = _gather(torch, fa, np.where(inside, off + src, off)).copy()
+        g = gather_columns(torch, fa, np.where(inside, off + src, off)).copy()
         fin = O.equilibrium_f(np.array(d["rho_in"]), np.array(d["u_in"]), np.array(d["theta_in"]), model)
         fout = O.equilibrium_f(np.array(d["rho_out"]), np.array(d["u_out"]), np.array(d["theta_out"]), model)
         g = np.where(src < 0, fin[:, None], np.where(src >= nx, fout[:, None], g))
