@@ -537,6 +537,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5000)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-contraction and adjoint timings")
+    ap.add_argument("--variants", default="moment_state,forms,shock_adjoint,batched",
+                    help="comma list of the variant groups to time after the main step: moment_state, forms "
+                         "(other contraction forms, additive collision, adjoint), shock_adjoint, batched")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain device copy of one f buffer instead (HBM calibration)")
     args = ap.parse_args()
@@ -595,10 +598,14 @@ def main():
     rho = lat.moments(cur)[0]
     assert torch.isfinite(rho).all() and abs(float(rho.mean()) - 1.0) < 1e-3
     variants = {}
-    if not args.no_variants:
+    groups = set() if args.no_variants else {g.strip() for g in args.variants.split(",") if g.strip()}
+    if "moment_state" in groups:
         variants["moment_state"] = time_moment_state(torch, lat, cur, fb if cur is fa else fa, args.steps, ms_step)
+    if "forms" in groups:
         variants.update(time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step))
+    if "shock_adjoint" in groups:
         variants["shock_adjoint"] = time_shock_adjoint(torch)
+    if "batched" in groups:
         variants["batched_mach_sweep"] = time_batched(torch, steps=args.batched_steps)
 
     out = {

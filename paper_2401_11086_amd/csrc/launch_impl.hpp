@@ -174,8 +174,12 @@ void Launch<Q1, N>::ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, fl
                          dim3(256), 0, s, G, src, t1, Tz);
       hipLaunchKernelGGL((k_ms_pass_y<Q1, N>), dim3(static_cast<unsigned>((ly + 255) / 256), (G.ny + Ty - 1) / Ty),
                          dim3(256), 0, s, G, t1, t2, Ty);
-      hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s, c->L,
-                         G, t2, dst);
+      if (G.nx % 64 == 0 && G.k[0] == 0)
+        hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N, true>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s,
+                           c->L, G, t2, dst);
+      else
+        hipLaunchKernelGGL((k_ms_pass_x_collide<Q1, N, false>), dim3((G.nx + 255) / 256, G.ny, G.nz), dim3(256), 0, s,
+                           c->L, G, t2, dst);
     }
   }
 

@@ -231,9 +231,49 @@ constexpr int group_index(int N, int BY, int BZ) {
 #define LBSMRT_GROUPS_PER_PHASE 3
 #endif
 constexpr int kGroupsPerPhase = LBSMRT_GROUPS_PER_PHASE;
+#ifndef LBSMRT_GROUPS_PER_PHASE_ROW
+#define LBSMRT_GROUPS_PER_PHASE_ROW 5
+#endif
+constexpr int kGroupsPerPhaseRow = LBSMRT_GROUPS_PER_PHASE_ROW;   // two loads per field instead of 2 p + 1
+// Share of pass x's groups whose taps move across lanes on whole rows (the rest are loaded):
+// measured on the 256^3 D3Q343 box, 0, 1/3, 1/2, 2/3 of the groups: 6.11, 6.01, 5.95, 5.74 ms
+// per moment-state step (one unit, one run); the 160^3 D3Q729 box is unchanged (3.30 ms).
+#ifndef LBSMRT_ROW_GROUPS_NUM
+#define LBSMRT_ROW_GROUPS_NUM 2
+#define LBSMRT_ROW_GROUPS_DEN 3
+#endif
 
 // One (by, bz) group of pass x: a[bx, by, bz] = sum_ax sum_e K_{bx ax}(e) t2[ax, by, bz](x - e - k_x)
 // for bx <= N - by - bz, in FP64, each tap pair factored through the rebuilt populations.
+// Row neighbours of a wave that covers 64 consecutive x of one row (nx a multiple of 64, no x
+// shift): lane l holds v = row[x0 + l] and a halo value h (lanes 0 .. H-1: row[x0 - 1 - l], lanes
+// 64 - H .. 63: row[x0 + 127 - l], periodic).  wave_shr:1 moves every lane's value one lane up and
+// leaves lane 0 its old value, wave_shl:1 one lane down leaving lane 63's; so R[d] = row[x0 + l - d]
+// and Lf[d] = row[x0 + l + d] are built d lanes at a time, the halo shifted into lanes 0 and 63.
+__device__ __forceinline__ float wave_shr1(float old, float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, src), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_shl1(float old, float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, src), 0x130, 0xf, 0xf, false));
+}
+template <int H>
+__device__ __forceinline__ void row_neighbours(float v, float h, float (&R)[H + 1], float (&Lf)[H + 1]) {
+  R[0] = v;
+  Lf[0] = v;
+  float hl = h, hr = h;
+#pragma unroll
+  for (int d = 1; d <= H; ++d) {
+    R[d] = wave_shr1(hl, R[d - 1]);
+    Lf[d] = wave_shl1(hr, Lf[d - 1]);
+    if (d < H) {
+      hl = wave_shl1(hl, hl);
+      hr = wave_shr1(hr, hr);
+    }
+  }
+}
+
 template <int Q1, int N, int BY, int BZ>
 __device__ __forceinline__ void x_group(const LatticeConst& L, const float* __restrict__ t2, long long stride,
                                         const unsigned (&op)[Taps1D<Q1>::p + 1],
@@ -298,9 +338,105 @@ __device__ __forceinline__ void x_groups(const LatticeConst& L, const float* __r
   }
 }
 
+// ---- pass x on whole 64-lane rows: tap sources moved across lanes
+// Group g (compile-time order of group_index) -> (by, bz).
+// (g = n_sym(N), one past the last group, maps to (N + 1, 0).)
+constexpr int group_by(int N, int g) {
+  int by = 0;
+  while (by <= N && g > N - by) {
+    g -= N - by + 1;
+    ++by;
+  }
+  return by;
+}
+constexpr int group_bz(int N, int g) {
+  int by = 0;
+  while (by <= N && g > N - by) {
+    g -= N - by + 1;
+    ++by;
+  }
+  return g;
+}
+
+// One group (BY, BZ) from this lane's row and halo values of its N + 1 input fields.
+template <int Q1, int N, int BY, int BZ>
+__device__ __forceinline__ void x_group_row(const float (&rv)[N + 1], const float (&rh)[N + 1],
+                                            float (&a32)[n_moments(N)]) {
+  using S = Taps1D<Q1>;
+  constexpr int NO = N - BY - BZ;
+  float Rn[N + 1][S::H + 1], Ln[N + 1][S::H + 1];
+#pragma unroll
+  for (int a = 0; a <= N; ++a) row_neighbours<S::H>(rv[a], rh[a], Rn[a], Ln[a]);
+  double acc[NO + 1];
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
+  {
+    double c = 0.0;                           // centre tap: even orders only
+#pragma unroll
+    for (int a = 0; a <= N; a += 2) c = fma(tab_rw<Q1>(0, a), static_cast<double>(rv[a]), c);
+#pragma unroll
+    for (int b = 0; b <= NO; b += 2) acc[b] = fma(tab_he<Q1>(0, b), c, acc[b]);
+  }
+#pragma unroll
+  for (int t = 1; t <= S::p; ++t) {
+    double ev = 0.0, od = 0.0;
+#pragma unroll
+    for (int a = 0; a <= N; ++a) {
+      // tap +e pulls from x - e (lane l - e), tap -e from x + e; folded in FP32 as in x_group
+      const float vp = Rn[a][S::e[t]], vm = Ln[a][S::e[t]];
+      const double sm = static_cast<double>(vp + vm), df = static_cast<double>(vp - vm);
+      ev = fma(tab_rw<Q1>(t, a), (a & 1) ? df : sm, ev);
+      od = fma(tab_rw<Q1>(t, a), (a & 1) ? sm : df, od);
+    }
+#pragma unroll
+    for (int b = 0; b <= NO; ++b) acc[b] = fma(tab_he<Q1>(t, b), (b & 1) ? od : ev, acc[b]);
+  }
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) {
+    float v = static_cast<float>(acc[b]);
+    asm volatile("" : "+v"(v));
+    a32[midx(b, BY, BZ)] = v;
+  }
+}
+
+template <int Q1, int N, int G0, int I, int NG>
+__device__ __forceinline__ void x_phase_groups(const float (&rv)[NG][N + 1], const float (&rh)[NG][N + 1],
+                                               float (&a32)[n_moments(N)]) {
+  if constexpr (I < NG) {
+    x_group_row<Q1, N, group_by(N, G0 + I), group_bz(N, G0 + I)>(rv[I], rh[I], a32);
+    x_phase_groups<Q1, N, G0, I + 1, NG>(rv, rh, a32);
+  }
+}
+
+// Groups G0 .. G0 + G - 1 as one phase: the row and halo values of all their input fields are
+// loaded first (two loads per field, all in flight together), then the groups are reduced; the
+// sums' pins end the phase, so each phase is one memory round trip.
+template <int Q1, int N, int G0, int G, int GEND>
+__device__ __forceinline__ void x_phases_row(const float* __restrict__ t2, long long stride, unsigned own,
+                                             unsigned hoff, float (&a32)[n_moments(N)]) {
+  constexpr int P2 = n_sym(N);
+  if constexpr (G0 < GEND) {
+    constexpr int NG = G0 + G <= GEND ? G : GEND - G0;
+    float rv[NG][N + 1], rh[NG][N + 1];
+#pragma unroll
+    for (int i = 0; i < NG; ++i)
+#pragma unroll
+      for (int a = 0; a <= N; ++a) {
+        const float* __restrict__ row =
+            t2 + static_cast<size_t>(a * P2 + pair_pos(group_by(N, G0 + i), group_bz(N, G0 + i))) * stride;
+        rv[i][a] = load_at(row, own);
+        rh[i][a] = load_at(row, hoff);
+      }
+    x_phase_groups<Q1, N, G0, 0, NG>(rv, rh, a32);
+    x_phases_row<Q1, N, G0 + G, G, GEND>(t2, stride, own, hoff, a32);
+  }
+}
+
 // Pass x + collision: t2[ax P2 + pair(by, bz)] -> a[bx, by, bz], SMRT collision (FP64), store a'.
-// Grid (ceil(nx/256), ny, nz).
-template <int Q1, int N>
+// Grid (ceil(nx/256), ny, nz).  ROW (nx a multiple of 64, k_x = 0): the tap sources are moved
+// across the wave's lanes (row_neighbours) instead of loaded one by one; every wave is then either
+// entirely inside the row or entirely past its end.
+template <int Q1, int N, bool ROW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_pass_x_collide(
     LatticeConst L, MsGeom G, const float* __restrict__ t2, float* __restrict__ m_out) {
   using S = Taps1D<Q1>;
@@ -310,6 +446,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
   const int y = static_cast<int>(blockIdx.y);
   const int z = static_cast<int>(blockIdx.z);
   const int row = G.nx * (y + G.ny * z);
+  unsigned hoff = 0;
+  if constexpr (ROW) {
+    const int l = static_cast<int>(threadIdx.x) & 63;
+    const int x0 = x - l;
+    int hx = l < S::H ? x0 - 1 - l : (l >= 64 - S::H ? x0 + 127 - l : x);
+    hx %= G.nx;
+    hx += hx < 0 ? G.nx : 0;
+    hoff = static_cast<unsigned>(row + hx) * 4u;
+  }
   // byte offsets of the sources x - e - k_x (tap +e) and x + e - k_x (tap -e)
   unsigned op[S::p + 1], om[S::p + 1];
 #pragma unroll
@@ -322,7 +467,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 
     om[t] = static_cast<unsigned>(row + sm) * 4u;
   }
   float a32[M];
-  x_groups<Q1, N, 0, 0>(L, t2, G.stride, op, om, a32);
+  if constexpr (ROW) {
+    // the first kRowGroups groups take their taps across lanes (vector ALU), the rest by loads
+    // (texture-address unit), so that neither unit carries the whole pass
+    constexpr int kRowGroups = LBSMRT_ROW_GROUPS_NUM * n_sym(N) / LBSMRT_ROW_GROUPS_DEN;
+    x_phases_row<Q1, N, 0, kGroupsPerPhaseRow, kRowGroups>(t2, G.stride, op[0], hoff, a32);
+    x_groups<Q1, N, group_by(N, kRowGroups), group_bz(N, kRowGroups)>(L, t2, G.stride, op, om, a32);
+  } else {
+    x_groups<Q1, N, 0, 0>(L, t2, G.stride, op, om, a32);
+  }
   double d[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);

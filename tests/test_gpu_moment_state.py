@@ -67,6 +67,12 @@ CASES = [
     ("q729_n4_13x11x12", D1Q9, 4, (13, 11, 12), (0, 0, 0)),
     ("q729_n5_12x10x46", D1Q9, 5, (12, 10, 46), (0, 0, 0)),
     ("q343_n4_300x3x2", D1Q7, 4, (300, 3, 2), (0, 0, 0)),
+    # rows of whole 64-lane waves: pass x takes its taps from the wave's own row values
+    ("q343_n4_row_64x6x5", D1Q7, 4, (64, 6, 5), (0, 0, 0)),
+    ("q343_n3_row_128x3x2", D1Q7, 3, (128, 3, 2), (0, 0, 0)),
+    ("q729_n4_row_64x5x4", D1Q9, 4, (64, 5, 4), (0, 0, 0)),
+    ("q729_n5_row_192x3x3", D1Q9, 5, (192, 3, 3), (0, 0, 0)),
+    ("q343_n4_shift_64x5x4", D1Q7, 4, (64, 5, 4), (1, 0, 0)),
 ]
 
 
@@ -88,6 +94,26 @@ def test_moment_state_matches_population_step(torch, name, stencil, N, shape, sh
     b = f_pop[:, :n].double()
     err = float((a - b).abs().max() / b.abs().max())
     print(f"{name}: {steps} steps, moment state vs population state {err:.2e}")
+    assert err < TOL_STEP, err
+
+
+@pytest.mark.parametrize("stencil,N", [(D1Q7, 4), (D1Q9, 5)], ids=["q343_n4", "q729_n5"])
+def test_moment_state_row_box_one_step_matches_oracle(torch, stencil, N):
+    """A 64 x 4 x 3 box (whole 64-lane rows, the cross-lane form of pass x), one step from a noisy
+    moment state, against the oracle's step of the expanded populations."""
+    shape = (64, 4, 3)
+    lat, vs, tau = _lattice(stencil, N, shape)
+    n = lat.n_nodes
+    m0 = _noisy_moments(torch, lat, _fields(shape, (0, 0, 0), vs.r, seed=11), seed=12)
+    f0 = lat.expand_state(m0)
+    m1 = lat.step_moment_state(m0, lat.new_moment_state(), lat.new_moment_work(), 1)
+    lat.sync()
+    g = lat.expand_state(m1)[:, :n].double().cpu().numpy()
+    fo0 = f0[:, :n].double().cpu().numpy().reshape(-1, 3, 4, 64)
+    model = O.Model(vs=vs, N=N, tau=tau, shift=(0, 0, 0))
+    fo1 = O.step(fo0, model, O.Domain(nx=64, ny=4, nz=3, bc_x=0)).reshape(g.shape)
+    err = float(np.abs(g - fo1).max() / np.abs(fo1).max())
+    print(f"64x4x3 box, one moment-state step vs FP64 oracle: {err:.2e}")
     assert err < TOL_STEP, err
 
 
