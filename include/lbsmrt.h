@@ -284,6 +284,10 @@ lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* ctx, const float* m, float* f, voi
  * line); none of m_a, m_b, work may overlap.  E_UNSUPPORTED unless the context has exactly one
  * periodic domain (bc_x = 0) or only line domains (ny = nz = 1, any bc_x, any number), the
  * rebuilt collision, and the stencil D1Q7 {0, +-1, +-2, +-3} or D1Q9 {0, +-1, +-2, +-3, +-5}.
+ * The context's launch setting applies: in LBSMRT_LAUNCH_GRAPH mode `graph_steps` steps are
+ * captured once per (m_a, m_b, work) and replayed (recaptured when any of them, the launch
+ * settings or the relaxation times change); lanes_per_node >= 4 runs line domains with eight
+ * lanes per node; the persistent mode launches directly.  E_HIP if a capture fails.
  * Validity failures latch the flag read by lbsmrt_sync_status.  Asynchronous. */
 lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* ctx, float* m_a, float* m_b, float* work, int n_steps,
                                        void* stream);

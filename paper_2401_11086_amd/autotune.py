@@ -2,7 +2,10 @@
 by timing a few steps of the caller's own lattice, and caches the choice in a JSON file
 keyed by device, velocity set, order, precision, collision form, problem-size bucket and a
 digest of the domain geometry (shapes and boundary types), so that a choice made for shock
-tubes is never replayed on periodic domains of the same size."""
+tubes is never replayed on periodic domains of the same size.  autotune() tunes the population
+step (lbsmrt_step), autotune_moment_state() the moment-state step (lbsmrt_step_moment_state:
+direct or captured launches, one or eight lanes per node on line domains); the launch setting is
+one per context, so the last call's choice holds for both forms."""
 import hashlib
 import json
 import math
@@ -34,14 +37,14 @@ def _geometry_digest(lat):
     return h.hexdigest()[:16]
 
 
-def _key(lat):
+def _key(lat, form_suffix=""):
     props = torch.cuda.get_device_properties(lat.device)
     arch = getattr(props, "gcnArchName", props.name)
     bucket = int(round(math.log2(max(lat.n_nodes, 1))))
     shock = int(any(int(d.get("bc_x", 0)) != 0 for d in lat.domains))
     form = "rebuilt" if lat.regularized else "additive"
     return (f"{arch}|Q{lat.Q}|N{lat.N}|{lat.precision}|{form}|nodes2^{bucket}|dom{len(lat.domains)}"
-            f"|shock{shock}|geom{_geometry_digest(lat)}|lpn")
+            f"|shock{shock}|geom{_geometry_digest(lat)}|lpn{form_suffix}")
 
 
 def _time(lat, fa, fb, steps):
@@ -95,3 +98,60 @@ def autotune(lat, fa, fb, steps=20, graph_steps=32, use_cache=True):
             pass
     return dict(best, trials=[{"mode": m, "block": b, "lanes_per_node": k, "ms": round(t, 5)}
                               for m, b, k, t in trials], cached=False)
+
+
+def _time_ms(lat, ma, mb, work, steps):
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat.step_moment_state(ma, mb, work, 2)
+    torch.cuda.synchronize()
+    ev0.record()
+    lat.step_moment_state(ma, mb, work, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    lat.sync()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def autotune_moment_state(lat, ma, mb, work, steps=40, graph_steps=32, use_cache=True):
+    """Time the moment-state step's candidates on (ma, mb) (advanced in place): direct or
+    graph-captured launches, and on line domains one or eight lanes per node where the context
+    allows more than one; apply the fastest and return it as autotune() does."""
+    path = _cache_path()
+    key = _key(lat, "|moment_state")
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        best = cache[key]
+        try:
+            lat.set_launch(best["mode"], 0, graph_steps, best["lanes_per_node"])
+            return dict(best, cached=True)
+        except Exception:
+            pass
+    lines = all(int(d.get("ny", 1)) == 1 and int(d.get("nz", 1)) == 1 for d in lat.domains)
+    lanes = (1, 8) if lines and any(c[2] > 1 for c in _candidates(lat)) else (1,)
+    trials = []
+    for mode in ("direct", "graph"):
+        for lpn in lanes:
+            try:
+                lat.set_launch(mode, 0, graph_steps, lpn)
+            except Exception:
+                continue
+            trials.append((mode, lpn, _time_ms(lat, ma, mb, work, steps)))
+    mode, lpn, ms = min(trials, key=lambda t: t[2])
+    lat.set_launch(mode, 0, graph_steps, lpn)
+    best = {"mode": mode, "lanes_per_node": lpn, "ms_per_step": round(ms, 5)}
+    if use_cache:
+        cache[key] = best
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return dict(best, trials=[{"mode": m, "lanes_per_node": k, "ms": round(t, 5)} for m, k, t in trials],
+                cached=False)

@@ -50,6 +50,10 @@ struct lbsmrt_ctx {
   const float* graph_a = nullptr;
   const float* graph_b = nullptr;
   int graph_pairs = 0;
+  hipGraphExec_t ms_graph = nullptr; // the same for lbsmrt_step_moment_state (its two state buffers
+  const float* ms_graph_a = nullptr; // and the work buffer it was captured with)
+  const float* ms_graph_b = nullptr;
+  const float* ms_graph_w = nullptr;
   int n_blocks_adj = 0;
   int precision = LBSMRT_FP32;
   bool additive = false;              // f* = g + R (a' - a) instead of the rebuild (regularized = 0)

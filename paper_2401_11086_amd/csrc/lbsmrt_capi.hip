@@ -70,6 +70,27 @@ void drop_graph(lbsmrt_ctx* c) {
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   c->graph = nullptr;
   c->graph_a = c->graph_b = nullptr;
+  if (c->ms_graph) (void)hipGraphExecDestroy(c->ms_graph);
+  c->ms_graph = nullptr;
+  c->ms_graph_a = c->ms_graph_b = c->ms_graph_w = nullptr;
+}
+
+// Capture 2 graph_pairs calls of step(t, stream) (t = 0, 1, ...) on a private stream into an
+// executable graph; false if any stage fails.
+template <class StepFn>
+bool capture_steps(int n, hipGraphExec_t* out, StepFn step) {
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return false;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (int t = 0; t < n; ++t) step(t, cs);
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess;
+  }
+  if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  return ok;
 }
 
 void free_ctx(lbsmrt_ctx* c) {
@@ -476,22 +497,13 @@ lbsmrt_status lbsmrt_step(lbsmrt_ctx* c, float* f_a, float* f_b, int n_steps, vo
   }
   if (c->mode == LBSMRT_LAUNCH_GRAPH && n_steps >= 2 * c->graph_pairs) {
     if (!c->graph || c->graph_a != f_a || c->graph_b != f_b) {
-      drop_graph(c);
-      hipStream_t cs = nullptr;
-      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LBSMRT_E_HIP;
-      hipGraph_t g = nullptr;
-      bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-      if (ok) {
-        for (int t = 0; t < 2 * c->graph_pairs; ++t) {
-          const float* src = (t & 1) ? f_b : f_a;
-          float* dst = (t & 1) ? f_a : f_b;
-          dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::step(c, A, src, dst, cs); });
-        }
-        ok = hipStreamEndCapture(cs, &g) == hipSuccess;
-      }
-      if (ok) ok = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0) == hipSuccess;
-      if (g) (void)hipGraphDestroy(g);
-      (void)hipStreamDestroy(cs);
+      if (c->graph) (void)hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+      const bool ok = capture_steps(2 * c->graph_pairs, &c->graph, [&](int t, hipStream_t cs) {
+        const float* src = (t & 1) ? f_b : f_a;
+        float* dst = (t & 1) ? f_a : f_b;
+        dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::step(c, A, src, dst, cs); });
+      });
       if (!ok) { drop_graph(c); return LBSMRT_E_HIP; }
       c->graph_a = f_a;
       c->graph_b = f_b;
@@ -691,29 +703,50 @@ lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* c, float* m_a, float* m_b, fl
   if (!c->ms_lines && (overlap(m_a, mb, work, 2 * half * sizeof(float)) || overlap(m_b, mb, work, 2 * half * sizeof(float))))
     return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (c->ms_lines) {
-    const StepArgs A = step_args(c);
-    for (int t = 0; t < n_steps; ++t) {
-      const float* src = (t & 1) ? m_b : m_a;
-      float* dst = (t & 1) ? m_a : m_b;
-      dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_line_step(c, A, src, dst, s); });
-    }
-    return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
+  const StepArgs A = step_args(c);
+  MsGeom G{};
+  if (!c->ms_lines) {
+    const lbsmrt_domain& D = c->doms[0];
+    G.nx = D.nx; G.ny = D.ny; G.nz = D.nz;
+    for (int k = 0; k < 3; ++k) G.k[k] = c->L.k[k];
+    G.stride = c->stride;
+    G.tsc = D.tau_scale > 0.0 ? D.tau_scale : 1.0;
+    G.err = c->d_err;
   }
-  const lbsmrt_domain& D = c->doms[0];
-  MsGeom G;
-  G.nx = D.nx; G.ny = D.ny; G.nz = D.nz;
-  for (int k = 0; k < 3; ++k) G.k[k] = c->L.k[k];
-  G.stride = c->stride;
-  G.tsc = D.tau_scale > 0.0 ? D.tau_scale : 1.0;
-  G.err = c->d_err;
   float* t1 = work;
-  float* t2 = work + half;
-  for (int t = 0; t < n_steps; ++t) {
+  float* t2 = work ? work + half : nullptr;
+  // step t of the call: line domains run the x-stage kernel, a periodic box its three passes
+  auto one = [&](int t, hipStream_t st) {
     const float* src = (t & 1) ? m_b : m_a;
     float* dst = (t & 1) ? m_a : m_b;
-    dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_step(c, G, src, dst, t1, t2, s); });
+    if (c->ms_lines)
+      dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_line_step(c, A, src, dst, st); });
+    else
+      dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::ms_step(c, G, src, dst, t1, t2, st); });
+  };
+  int done = 0;
+  if (c->mode == LBSMRT_LAUNCH_GRAPH && n_steps >= 2 * c->graph_pairs) {
+    // the launch setting's graph mode: 2 graph_pairs steps captured once per (m_a, m_b, work)
+    const float* w = c->ms_lines ? nullptr : work;
+    if (!c->ms_graph || c->ms_graph_a != m_a || c->ms_graph_b != m_b || c->ms_graph_w != w) {
+      if (c->ms_graph) (void)hipGraphExecDestroy(c->ms_graph);
+      c->ms_graph = nullptr;
+      if (!capture_steps(2 * c->graph_pairs, &c->ms_graph, one)) {
+        c->ms_graph = nullptr;
+        c->ms_graph_a = c->ms_graph_b = c->ms_graph_w = nullptr;
+        return LBSMRT_E_HIP;
+      }
+      c->ms_graph_a = m_a;
+      c->ms_graph_b = m_b;
+      c->ms_graph_w = w;
+    }
+    const int per = 2 * c->graph_pairs;
+    const int reps = n_steps / per;
+    for (int r = 0; r < reps; ++r)
+      if (hipGraphLaunch(c->ms_graph, s) != hipSuccess) return LBSMRT_E_HIP;
+    done = reps * per;   // even: the state is back in m_a
   }
+  for (int t = done; t < n_steps; ++t) one(t - done, s);
   return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
 }
 

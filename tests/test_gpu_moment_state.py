@@ -419,3 +419,51 @@ def test_uniform_state_is_a_fixed_point(torch, name, stencil, N, shape, lanes):
     print(f"{name}: uniform equilibrium after 100 steps moved by {err:.2e}, non-uniformity {spread:.2e}")
     assert err < 1e-6, err
     assert spread == 0.0, spread       # every node sees the same arithmetic
+
+
+@pytest.mark.parametrize("kind", ["line_batch", "box"])
+def test_graph_mode_replays_match_direct(torch, kind):
+    """The moment-state step in graph mode (8 steps captured) against direct launches, bitwise:
+    three calls of 10 steps (one replay plus two direct steps each), eager work and
+    synchronisations between them, every call's result compared; then a relaxation-time change
+    must recapture (the replayed graph would hold the old times)."""
+    if kind == "line_batch":
+        lat, fields = _line_case(D1Q9, 5, [(1.5, 90), (3.0, 130), (2.2, 70)])
+    else:
+        lat, _, _ = _lattice(D1Q7, 4, (64, 6, 5))
+        fields = _fields((64, 6, 5), (0, 0, 0), lat.c_l, seed=41)
+    n = lat.n_nodes
+    m0 = _noisy_moments(torch, lat, fields, seed=42)
+    work = lat.new_moment_work()
+    outs = {}
+    for mode in ("direct", "graph"):
+        lat.set_launch(mode, 0, 8, 0)
+        ma, mb = m0.clone(), lat.new_moment_state()
+        res = []
+        for call in range(3):
+            cur = lat.step_moment_state(ma, mb, work, 10)
+            lat.sync()
+            assert cur is ma                          # an even step count returns to m_a
+            res.append(ma[:, :n].clone())
+            torch.cuda.synchronize()
+            _ = (ma[:, :n] * 2.0).sum().item()       # eager work between the replays
+        if mode == "graph":
+            tau = {k: v * 1.1 for k, v in lat.tau.items()}
+            lat.set_tau(tau)
+            cur = lat.step_moment_state(ma, mb, work, 10)
+            lat.sync()
+            res.append(ma[:, :n].clone())
+            lat.set_tau({k: v / 1.1 for k, v in tau.items()})
+        outs[mode] = res
+    lat.set_launch("direct", 0, 8, 0)
+    for a, b in zip(outs["direct"], outs["graph"]):
+        assert torch.equal(a, b)
+    # direct launches with the changed times from the same state as the graph's fourth call
+    ma, mb = outs["direct"][-1].clone(), lat.new_moment_state()
+    full = torch.zeros_like(m0)
+    full[:, :n] = ma
+    tau = {k: v * 1.1 for k, v in lat.tau.items()}
+    lat.set_tau(tau)
+    lat.step_moment_state(full, mb, work, 10)
+    lat.sync()
+    assert torch.equal(full[:, :n], outs["graph"][-1])
