@@ -17,8 +17,8 @@
 namespace lbsmrt {
 
 // Transpose of axis_transform<N,AXIS>:  xb_g = sum_{b >= g} C(b, g) P_{b-g} yb_b  (in place, bottom-up)
-template <int N, int AXIS>
-__device__ __forceinline__ void axis_transform_T(double* d, const double (&P)[N + 1]) {
+template <int N, int AXIS, class D>
+__device__ __forceinline__ void axis_transform_T(D d, const double (&P)[N + 1]) {
 #pragma unroll
   for (int o1 = 0; o1 <= N; ++o1)
 #pragma unroll
@@ -59,9 +59,9 @@ __host__ __device__ constexpr double multiplicity(int a, int b, int c) {
 //    sensitivities of a' = T_A z are zbar . (L_k z) and zbar . (sum_k L_k^2 z)/2 with zbar = T_A^T abar;
 //  * the irreducible projectors are self-adjoint in the full-contraction inner product
 //    (weights W = n!/alpha!), so the transposed relaxation is W K W^{-1}.
-template <int N, class V>
+template <int N, class V, class AB>
 __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro& mac, const V& dv, const V& zv,
-                                             double* ab, double* tb) {
+                                             AB ab, double* tb) {
   const double rho = mac.rho, th = mac.th;
   const double u[3] = {mac.ux, mac.uy, mac.uz};
   const double sc = mac.tsc * (L.density_scaling ? L.rho_ref / rho : 1.0);
@@ -153,12 +153,13 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
   for (int n = 2; n <= N; ++n) {
     double om[3];
     omegas(n, om);
-    double* y = ab + order_start(n);
+    // this order's components in a local array (ab may live in LDS): y = W^{-1} d'bar
+    double y[n_sym(kMaxN)];
 #pragma unroll
     for (int a = 0; a <= n; ++a)
 #pragma unroll
       for (int b = 0; b <= n; ++b)
-        if (a + b <= n) y[sym_pos(n, a, b)] *= 1.0 / multiplicity(a, b, n - a - b);
+        if (a + b <= n) y[sym_pos(n, a, b)] = ab[order_start(n) + sym_pos(n, a, b)] * (1.0 / multiplicity(a, b, n - a - b));
     constexpr int S2 = n_sym(kMaxN - 2);
     double Y1[S2], Y2[S2];
     if (n == 2) irreducible_part<2, 1>(y, Y1);
@@ -188,7 +189,7 @@ __device__ __forceinline__ void node_adjoint(const LatticeConst& L, const Macro&
         p0d += w * y[i] * di;
         pd1 += w * q1 * di;
         pd2 += w * q2 * di;
-        y[i] = ((1.0 - om[0]) * y[i] - c1 * q1 - c2 * q2) * w;
+        ab[order_start(n) + i] = ((1.0 - om[0]) * y[i] - c1 * q1 - c2 * q2) * w;
       }
     const double ob[3] = {-(p0d - pd1 - pd2), -pd1, -pd2};
 #pragma unroll

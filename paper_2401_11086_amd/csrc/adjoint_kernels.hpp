@@ -13,9 +13,8 @@ constexpr int kTauCols = (kMaxN + 1) * 3;   // dL/dtau[n][m] flattened as n*3+m
 // LPN > 1: each lane of a node's group scatters the slabs ix = sub, sub + LPN, ... with the
 // uniform pass count of gather_project64; a lane with no slab left repeats the last one, storing
 // the values its owner stores to the same addresses in the same instruction.
-template <int Q1, int N, bool SHOCK, int LPN = 1>
-LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull<Q1>& P,
-                                                             const double (&ab)[n_moments(N)],
+template <int Q1, int N, bool SHOCK, int LPN = 1, class AB>
+LBSMRT_PHASE void scatter_transpose_projection(const LatticeConst& L, const Pull<Q1>& P, const AB& ab,
                                                              float* __restrict__ out, long long stride) {
   constexpr int p = Q1 / 2;
   constexpr int P2 = n_sym(N);
@@ -142,19 +141,33 @@ __device__ __forceinline__ void block_sum_cols(double (&v)[C], double* red) {
 constexpr int kAdjBlock = 64;
 constexpr int kAdjRowBlock = 256;
 
-// Per-thread vector of M doubles in dynamic LDS, strided by the block size B (conflict-free);
-// the stride is a compile-time constant so that every element address is the thread's base plus
-// an immediate offset.
+// Vector of M doubles in dynamic LDS, one per node, strided by the number of nodes B of the
+// work-group (conflict-free); the stride is a compile-time constant so that every element address
+// is the node's base plus an immediate offset.  The LPN lanes of a node's group share it: they
+// hold bit-identical values (the group's sums are all-reduced) and write the same values.
 template <int B>
 struct LdsVec {
   double* base;
   __device__ __forceinline__ double operator()(int i) const { return base[i * B]; }
   __device__ __forceinline__ void set(int i, double v) const { base[i * B] = v; }
+  __device__ __forceinline__ double& operator[](int i) const { return base[i * B]; }
+  __device__ __forceinline__ LdsVec operator+(int k) const { return LdsVec{base + k * B}; }
 };
 
+// Dynamic LDS of the adjoint step per work-group of B work-items: d and z for each of its B / LPN
+// nodes, and at N >= 5 with a node split over lanes also the adjoint moments (56 doubles, which
+// in registers spill about 1 KB per work-item; with one lane per node they stay in registers, as
+// a third vector per work-item would leave one 64-item work-group per compute unit).
+template <int N, int LPN>
+constexpr bool adjoint_moments_in_lds() { return N >= 5 && LPN > 1; }
+template <int N, int LPN, int B>
+constexpr size_t adjoint_lds_bytes() {
+  return (adjoint_moments_in_lds<N, LPN>() ? 3 : 2) * sizeof(double) * n_moments(N) * (B / LPN);
+}
+
 // One adjoint step: lam_t = (d f_{t+1} / d f_t)^T lam_next, per-block partials of dL/dtau.
-// Dynamic LDS: 2 M doubles per work-item (the local moments d and z = Lambda d'); blocks of
-// kAdjBlock work-items.
+// Dynamic LDS (adjoint_lds_bytes): per node the local moments d and z = Lambda d', and at
+// N >= 5 with lanes per node the adjoint moments abar; blocks of kAdjBlock work-items.
 template <int Q1, int N, bool SHOCK, int LPN = 1, int B = kAdjBlock>
 __global__ __launch_bounds__(B) void k_adjoint(LatticeConst L, StepArgs A, const float* __restrict__ f_t,
                                                  const float* __restrict__ lam_next, float* __restrict__ lam_t,
@@ -169,8 +182,10 @@ __global__ __launch_bounds__(B) void k_adjoint(LatticeConst L, StepArgs A, const
 #pragma unroll
   for (int i = 0; i < NT; ++i) tb[i] = 0.0;
   if (active) {
-    const LdsVec<B> dv{lds + threadIdx.x};
-    const LdsVec<B> zv{lds + M * B + threadIdx.x};
+    constexpr int G = B / LPN;                       // nodes per work-group
+    const int g = static_cast<int>(threadIdx.x) / LPN;
+    const LdsVec<G> dv{lds + g};
+    const LdsVec<G> zv{lds + M * G + g};
     Macro mac;
     {
       double d[M];
@@ -183,10 +198,23 @@ __global__ __launch_bounds__(B) void k_adjoint(LatticeConst L, StepArgs A, const
 #pragma unroll
       for (int i = 0; i < M; ++i) dv.set(i, d[i]);
     }
-    double ab[M];
-    own_project64<Q1, N, true, LPN>(L, lam_next, A.stride, P.node, ab, P.sub);
-    node_adjoint<N>(L, mac, dv, zv, ab, tb);
-    scatter_transpose_projection<Q1, N, SHOCK, LPN>(L, P, ab, lam_t, A.stride);
+    if constexpr (adjoint_moments_in_lds<N, LPN>()) {
+      const LdsVec<G> av{lds + 2 * M * G + g};
+      {
+        double ab[M];
+        own_project64<Q1, N, true, LPN>(L, lam_next, A.stride, P.node, ab, P.sub);
+#pragma unroll
+        for (int i = 0; i < M; ++i) av.set(i, ab[i]);
+      }
+      node_adjoint<N>(L, mac, dv, zv, av, tb);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      scatter_transpose_projection<Q1, N, SHOCK, LPN>(L, P, av, lam_t, A.stride);
+    } else {
+      double ab[M];
+      own_project64<Q1, N, true, LPN>(L, lam_next, A.stride, P.node, ab, P.sub);
+      node_adjoint<N>(L, mac, dv, zv, ab, tb);
+      scatter_transpose_projection<Q1, N, SHOCK, LPN>(L, P, ab, lam_t, A.stride);
+    }
     // every lane of a group zeroes the same out-flowing populations (identical stores)
     if (SHOCK && P.bc_x == 1) zero_outflow<Q1>(L, P, lam_t, A.stride);
     if (LPN > 1 && P.sub != 0) {

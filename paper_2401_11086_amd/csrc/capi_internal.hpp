@@ -96,6 +96,9 @@ struct Launch {
                       double* partial, double* stage, hipStream_t s);
   // Raise the dynamic LDS limit of the 256-node periodic adjoint (N <= 4); false if refused.
   static bool allow_row_adjoint();
+  // Raise the dynamic LDS limit of the 64-item adjoint work-groups to what they take
+  // (adjoint_lds_bytes: above 64 KB with one lane per node at N = 5); false if refused.
+  static bool allow_adjoint_lds();
   static void loss_seed(lbsmrt_ctx* c, const StepArgs& A, const float* f, const double* target, const double* sc,
                         float* lam, hipStream_t s);
   // Moment-state form.  Line chunk of the z and y passes: a multiple of the tap window W, as long

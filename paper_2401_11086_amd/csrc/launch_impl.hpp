@@ -99,13 +99,11 @@ void Launch<Q1, N>::adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, 
     if constexpr (!kFull) {
       return;
     } else {
-      const size_t lds = 2 * sizeof(double) * n_moments(N) * kAdjBlock;
       const int nb = adjoint_groups(c);
       if constexpr (N <= 4) {
         if (!c->shock && c->n_blocks_adjR > 0) {
           hipLaunchKernelGGL((k_adjoint<Q1, N, false, 1, kAdjRowBlock>), dim3(nb), dim3(kAdjRowBlock),
-                             2 * sizeof(double) * n_moments(N) * kAdjRowBlock, s, c->L, A, f_t, lam_next, lam_t,
-                             partial);
+                             (adjoint_lds_bytes<N, 1, kAdjRowBlock>()), s, c->L, A, f_t, lam_next, lam_t, partial);
           hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, partial, nb, n_tau_slots(N),
                              stage);
           hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, stage, A.dtau);
@@ -113,26 +111,42 @@ void Launch<Q1, N>::adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, 
         }
       }
       if (c->shock && c->lpn == 8)
-        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, partial);
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), (adjoint_lds_bytes<N, 8, kAdjBlock>()),
+                           s, c->L, A, f_t, lam_next, lam_t, partial);
       else if (c->shock && c->lpn == 4)
-        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, partial);
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 4>), dim3(nb), dim3(kAdjBlock), (adjoint_lds_bytes<N, 4, kAdjBlock>()),
+                           s, c->L, A, f_t, lam_next, lam_t, partial);
       else if (c->shock)
-        hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, partial);
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true>), dim3(nb), dim3(kAdjBlock), (adjoint_lds_bytes<N, 1, kAdjBlock>()), s,
+                           c->L, A, f_t, lam_next, lam_t, partial);
       else
-        hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), lds, s, c->L, A, f_t, lam_next,
-                           lam_t, partial);
+        hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), (adjoint_lds_bytes<N, 1, kAdjBlock>()),
+                           s, c->L, A, f_t, lam_next, lam_t, partial);
       hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, partial, nb, n_tau_slots(N), stage);
       hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, stage, A.dtau);
     }
   }
 
 template <int Q1, int N>
+bool Launch<Q1, N>::allow_adjoint_lds() {
+    if constexpr (!kFull) {
+      return true;
+    } else {
+      auto raise = [](const void* fn, size_t bytes) {
+        return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)) ==
+               hipSuccess;
+      };
+      return raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true, 8>), adjoint_lds_bytes<N, 8, kAdjBlock>()) &&
+             raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true, 4>), adjoint_lds_bytes<N, 4, kAdjBlock>()) &&
+             raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true>), adjoint_lds_bytes<N, 1, kAdjBlock>()) &&
+             raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, false>), adjoint_lds_bytes<N, 1, kAdjBlock>());
+    }
+  }
+
+template <int Q1, int N>
 bool Launch<Q1, N>::allow_row_adjoint() {
     if constexpr (N <= 4) {
-      const int bytes = static_cast<int>(2 * sizeof(double) * n_moments(N) * kAdjRowBlock);
+      const int bytes = static_cast<int>(adjoint_lds_bytes<N, 1, kAdjRowBlock>());
       return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adjoint<Q1, N, false, 1, kAdjRowBlock>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
     }

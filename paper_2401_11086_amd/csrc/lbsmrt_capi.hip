@@ -351,6 +351,11 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
     }
   }
   c->n_blocks_adjR = static_cast<int>(blaR.size());
+  {
+    bool ok = true;
+    dispatch(c->Q1, c->N, [&](auto l) { ok = decltype(l)::allow_adjoint_lds(); });
+    if (!ok) { free_ctx(c); return LBSMRT_E_HIP; }
+  }
   const size_t partial_rows =
       static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8, c->n_blocks_adjR}));
   c->n_ghost = 2 * n_domains;

@@ -330,7 +330,7 @@ def _golden_steps(path):
     raise ValueError(path)
 
 
-@pytest.mark.parametrize("precision", ["fp64_contract", "fp32", "split_bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64_contract", "fp32", "split_bf16x3", "moment_state"])
 @pytest.mark.parametrize("name", list(STEADY_729))
 def test_d3q729_steady_profile_matches_oracle(torch, name, precision):
     """The high-Mach cases on D3Q729, N = 5 (Sec. 4.2 tubes, Table 3 theta1): Ma 7 with the Table 4
@@ -339,9 +339,10 @@ def test_d3q729_steady_profile_matches_oracle(torch, name, precision):
     tube whose tails reach the fixed ends creeps, so the step count is repeated rather than the
     stopping rule), from the same tanh profile.  Normalised rho, theta, q_x, each held relative to
     its own range (q_hat = q_x / (rho1 theta1^{3/2}) reaches 118 at Ma 7, rho_hat and theta_hat 1):
-    within 1e-4 as computed with FP64 contractions; for every contraction form within 1e-4 after
-    aligning the rho_hat = 1/2 crossings, with the shock offset below 0.01 cells (a shock between
-    fixed ends is translation-neutral: a small mass bias of the float32 contractions moves it)."""
+    within 1e-4 as computed with FP64 contractions and in the moment-state form (FP64 taps); for
+    every form within 1e-4 after aligning the rho_hat = 1/2 crossings, with the shock offset below
+    0.01 cells (a shock between fixed ends is translation-neutral: a small mass bias of the float32
+    contractions moves it)."""
     from paper_2401_11086_amd import _lib as C
     from paper_2401_11086_amd.presets import preset
     mach, nx, table = STEADY_729[name]
@@ -353,10 +354,17 @@ def test_d3q729_steady_profile_matches_oracle(torch, name, precision):
         tab = dict(preset(table))
         tab[(2, 1)] = tab[(2, 0)]
     case = shock_case(mach, nx, D1Q9, 5, table=tab)
-    lat = _lattice(case, precision)
+    lat = _lattice(case, "fp64_contract" if precision == "moment_state" else precision)
     fa = _gpu_state(torch, lat, case)
     fb = lat.new_state()
-    f = lat.step(fa, fb, steps)
+    if precision == "moment_state":
+        # the state held as the M moments of each node (the line kernel), expanded at the end
+        ma = lat.project_state(fa)
+        m = lat.step_moment_state(ma, lat.new_moment_state(), lat.new_moment_work(), steps)
+        lat.sync()
+        f = lat.expand_state(m, out=fb)
+    else:
+        f = lat.step(fa, fb, steps)
     lat.sync()
     g = _gpu_moments(lat, f, C.MOM_BASIC | C.MOM_Q)
     gn = _normalised(g[0], g[4], g[5], case["states"])
@@ -368,5 +376,5 @@ def test_d3q729_steady_profile_matches_oracle(torch, name, precision):
           + ", ".join(f"{e:.2e}" for e in raw) + "; aligned " + ", ".join(f"{e:.2e}" for e in aligned))
     assert abs(dx) < 1e-2, dx
     assert max(aligned) < TOL_PROFILE, aligned
-    if precision == "fp64_contract":
+    if precision in ("fp64_contract", "moment_state"):
         assert max(raw) < TOL_PROFILE, raw
