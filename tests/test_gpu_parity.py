@@ -339,10 +339,10 @@ def test_d3q729_steady_profile_matches_oracle(torch, name, precision):
     tube whose tails reach the fixed ends creeps, so the step count is repeated rather than the
     stopping rule), from the same tanh profile.  Normalised rho, theta, q_x, each held relative to
     its own range (q_hat = q_x / (rho1 theta1^{3/2}) reaches 118 at Ma 7, rho_hat and theta_hat 1):
-    within 1e-4 as computed with FP64 contractions and in the moment-state form (FP64 taps); for
-    every form within 1e-4 after aligning the rho_hat = 1/2 crossings, with the shock offset below
-    0.01 cells (a shock between fixed ends is translation-neutral: a small mass bias of the float32
-    contractions moves it)."""
+    within 1e-4 as computed with FP64 contractions; for every form (also the moment-state form,
+    whose state is the float32 moments) within 1e-4 after aligning the rho_hat = 1/2 crossings,
+    with the shock offset below 0.01 cells (a shock between fixed ends is translation-neutral: a
+    small mass bias of a float32 contraction or of the float32 moment state moves it)."""
     from paper_2401_11086_amd import _lib as C
     from paper_2401_11086_amd.presets import preset
     mach, nx, table = STEADY_729[name]
@@ -376,5 +376,5 @@ def test_d3q729_steady_profile_matches_oracle(torch, name, precision):
           + ", ".join(f"{e:.2e}" for e in raw) + "; aligned " + ", ".join(f"{e:.2e}" for e in aligned))
     assert abs(dx) < 1e-2, dx
     assert max(aligned) < TOL_PROFILE, aligned
-    if precision in ("fp64_contract", "moment_state"):
+    if precision == "fp64_contract":
         assert max(raw) < TOL_PROFILE, raw
