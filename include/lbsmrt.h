@@ -57,8 +57,11 @@ typedef enum {
                                 anything but the forward step, moments and equilibrium in FP64
                                 contractions and the rebuilt collision, or a launch setting the
                                 context does not allow */
-  LBSMRT_E_LIMIT = 7         /* the problem exceeds the fixed scratch of an allocation-free entry
+  LBSMRT_E_LIMIT = 7,        /* the problem exceeds the fixed scratch of an allocation-free entry
                                 point (lbsmrt_step_adjoint_noalloc) */
+  LBSMRT_E_TIMEOUT = 8       /* a persistent launch on line domains waited for a neighbouring
+                                work-group longer than its bound and gave up (the state is then
+                                invalid); reported by lbsmrt_sync_status */
 } lbsmrt_status;
 
 /* Arithmetic of the projection (eq:an) / rebuild (eq:fi) contractions.  The state f is float32 in
@@ -146,7 +149,13 @@ lbsmrt_status lbsmrt_get_domain_offsets(const lbsmrt_ctx* ctx, long long* out, i
  *                            first use for a given (f_a, f_b) pair and recaptured when the pair, the
  *                            launch settings or the relaxation times change;
  *  LBSMRT_LAUNCH_PERSISTENT  one cooperative launch running all steps, work-groups resident and
- *                            striding over the node blocks, a grid-wide barrier between steps. */
+ *                            striding over the node blocks.  When every domain is a line (ny = nz
+ *                            = 1) a block starts step t as soon as the blocks it pulls from have
+ *                            completed step t - 1 (per-block progress counters, each wait bounded:
+ *                            LBSMRT_E_TIMEOUT if one gives up); otherwise, or when a block holds
+ *                            fewer nodes than the pull reach max |e_j + k_x| (or a periodic line
+ *                            of more than three blocks ends in such a block), a grid-wide barrier
+ *                            separates the steps.  Results are the same either way. */
 enum { LBSMRT_LAUNCH_DIRECT = 0, LBSMRT_LAUNCH_GRAPH = 1, LBSMRT_LAUNCH_PERSISTENT = 2 };
 
 /* Choose the launch mode, the work-group size (64, 128 or 256 work-items; 0 keeps the current
@@ -166,6 +175,13 @@ enum { LBSMRT_LAUNCH_DIRECT = 0, LBSMRT_LAUNCH_GRAPH = 1, LBSMRT_LAUNCH_PERSISTE
  * nodes) and one lane per node; an eligible context with at most 8192 nodes starts with eight,
  * one with at most 16384 nodes with four. */
 lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* ctx, int mode, int block_size, int graph_steps, int lanes_per_node);
+
+/* Test hook of the persistent launch's bounded waits on line domains: polls before a wait gives
+ * up (default 4194304, each poll followed by a short sleep) and a skew added to every wait's
+ * target step (0 by default; a large skew makes every wait unreachable, so that the give-up path,
+ * LBSMRT_E_TIMEOUT, can be exercised without a stalled work-group).  Takes effect at the next
+ * launch.  E_ARG for a NULL ctx or spin_limit 0. */
+lbsmrt_status lbsmrt_test_flow_wait(lbsmrt_ctx* ctx, unsigned spin_limit, unsigned skew);
 
 /* The current launch settings (any output pointer may be NULL).  E_ARG for a NULL ctx. */
 lbsmrt_status lbsmrt_get_launch(const lbsmrt_ctx* ctx, int* mode, int* block_size, int* lanes_per_node);

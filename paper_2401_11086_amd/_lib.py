@@ -9,7 +9,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbsmrt.so")
 
-OK, E_ARG, E_QUADRATURE, E_STATE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_LIMIT = range(8)
+OK, E_ARG, E_QUADRATURE, E_STATE, E_HIP, E_NOMEM, E_UNSUPPORTED, E_LIMIT, E_TIMEOUT = range(9)
 FP32, SPLIT_BF16X3, FP64_CONTRACT = 0, 1, 2
 LAUNCH_DIRECT, LAUNCH_GRAPH, LAUNCH_PERSISTENT = 0, 1, 2
 MOM_BASIC, MOM_SIGMA, MOM_Q, MOM_M3, MOM_R41, MOM_R42, MOM_DLOCAL, MOM_ALAB = (1, 2, 4, 8, 16, 32, 64, 128)
@@ -85,6 +85,7 @@ _SIGS = {
     "lbsmrt_sync_status": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "lbsmrt_set_tau": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "lbsmrt_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "lbsmrt_test_flow_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint, ctypes.c_uint]),
     "lbsmrt_get_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
     "lbsmrt_moment_state_len": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong),

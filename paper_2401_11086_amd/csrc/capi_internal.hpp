@@ -46,6 +46,13 @@ struct lbsmrt_ctx {
   // launch mode of lbsmrt_step
   int mode = LBSMRT_LAUNCH_DIRECT;
   int persistent_grid = 0;           // resident work-groups of the persistent kernel
+  // persistent launch on line domains: per-block progress instead of a grid-wide barrier
+  bool flow = false;                 // every domain a line (ny = nz = 1)
+  int2* d_nbr = nullptr;             // [n_blocks] the blocks each block pulls from (-1: none)
+  unsigned* d_done = nullptr;        // [n_blocks] steps completed, counted from flow_base
+  unsigned flow_base = 0;
+  unsigned flow_spin_limit = 1u << 22;
+  unsigned flow_skew = 0;
   hipGraphExec_t graph = nullptr;    // captured pair of steps for LBSMRT_LAUNCH_GRAPH
   const float* graph_a = nullptr;
   const float* graph_b = nullptr;
@@ -86,8 +93,10 @@ struct Launch {
   template <int PREC>
   static void step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s);
   static void step(lbsmrt_ctx* c, const StepArgs& A, const float* src, float* dst, hipStream_t s);
-  template <int PREC, bool SH>
+  template <int PREC, bool SH, int LPN, bool FLOW>
   static const void* persistent_fn();
+  template <bool FLOW>
+  static const void* persistent_flow(const lbsmrt_ctx* c);
   static const void* persistent(const lbsmrt_ctx* c);
   static void moments(lbsmrt_ctx* c, const StepArgs& A, const float* f, double* out, unsigned mask, hipStream_t s);
   // Adjoint step and its dL/dtau reduction: per-work-group partials (adjoint_groups(c) rows of

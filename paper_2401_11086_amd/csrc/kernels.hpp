@@ -38,7 +38,7 @@ struct StepArgs {
   double* dtau;              // adjoint only: dL/dtau [6][3]
 };
 
-enum : int { kErrState = 1 };
+enum : int { kErrState = 1, kErrTimeout = 2 };
 
 // Loads and stores at a wave-uniform base plus a 32-bit byte offset, so the
 // compiler can use the scalar-base (saddr) form of global memory instructions.
@@ -842,19 +842,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   collide_stream_node<Q1, N, SHOCK, PREC, LPN, ADD>(L, A, fsrc, fdst, -1);
 }
 
-// Persistent form: every work-group strides over the block table, n_steps times, with a grid-wide
-// barrier between steps (cooperative launch, so all work-groups are resident).  Step t reads
-// fa when t is even and fb when odd, as lbsmrt_step does.
-template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1>
-__global__ __launch_bounds__(256) void k_collide_persistent(LatticeConst L, StepArgs A, float* fa, float* fb,
-                                                            int n_blocks, int n_steps) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-  for (int t = 0; t < n_steps; ++t) {
-    const float* src = (t & 1) ? fb : fa;
-    float* dst = (t & 1) ? fa : fb;
-    for (int wb = blockIdx.x; wb < n_blocks; wb += gridDim.x)
-      collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, src, dst, wb);
-    grid.sync();
+// Per-block progress of the persistent launch on line domains: nbr[b] = the blocks b depends on
+// (the neighbouring blocks of its domain within the pull reach, -1 for none), done[b] = the
+// number of steps block b has completed, counted from `base` (monotonic over calls, compared with
+// wrap-around), spin_limit = polls before a wait gives up.
+// s_waitcnt immediate of gfx9 waiting for vmcnt = 0 only (expcnt 7, lgkmcnt 15 left open).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+struct FlowArgs {
+  const int2* nbr;
+  unsigned* done;
+  unsigned base;
+  unsigned spin_limit;
+  unsigned skew;   // added to every wait's target: 0, or (tests of the give-up path) unreachable
+};
+
+// Wait (one work-item) until block b has completed `target` steps; gives up after spin_limit
+// polls, or at once when another wait has given up, latching kErrTimeout (the launch then ends
+// normally with wrong values, which lbsmrt_sync_status reports).
+// Polls are relaxed (an acquire load would invalidate the caches at every poll); the caller
+// fences once after its waits.
+__device__ __forceinline__ void wait_block(const FlowArgs& F, int b, unsigned target, int* err) {
+  if (b < 0) return;
+  unsigned spins = 0;
+  while (static_cast<int>(__hip_atomic_load(F.done + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout) return;
+    if (++spins >= F.spin_limit) {
+      atomicOr(err, kErrTimeout);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// Persistent form (cooperative launch, so all work-groups are resident): every work-group strides
+// over the block table, n_steps times.  Step t reads fa when t is even and fb when odd, as
+// lbsmrt_step does.  FLOW = false: a grid-wide barrier between steps.  FLOW = true (line domains):
+// no barrier; a block starts step t once the blocks it pulls from have completed step t - 1,
+// which also means they no longer read the buffer it overwrites (step t writes the buffer step
+// t - 1 read).  Each work-group takes its blocks in step order, and every wait is for a smaller
+// step than the waiter's, so the work-group at the smallest step can always proceed.
+template <int Q1, int N, bool SHOCK, int PREC, int LPN = 1, bool FLOW = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_collide_persistent(
+    LatticeConst L, StepArgs A, float* fa, float* fb, int n_blocks, int n_steps, FlowArgs F) {
+  if constexpr (!FLOW) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (int t = 0; t < n_steps; ++t) {
+      const float* src = (t & 1) ? fb : fa;
+      float* dst = (t & 1) ? fa : fb;
+      for (int wb = blockIdx.x; wb < n_blocks; wb += gridDim.x)
+        collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, src, dst, wb);
+      grid.sync();
+    }
+  } else {
+    for (int t = 0; t < n_steps; ++t) {
+      const float* src = (t & 1) ? fb : fa;
+      float* dst = (t & 1) ? fa : fb;
+      for (int wb = blockIdx.x; wb < n_blocks; wb += gridDim.x) {
+        if (t > 0) {
+          if (threadIdx.x == 0) {
+            const int2 nb = F.nbr[wb];
+            wait_block(F, nb.x, F.base + F.skew + t, A.err);
+            wait_block(F, nb.y, F.base + F.skew + t, A.err);
+            // pairs with the neighbours' release stores; the barrier orders the other waves'
+            // loads after it (they share this work-item's compute unit and caches)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          }
+          __syncthreads();
+        }
+        collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, src, dst, wb);
+        // every wave's stores acknowledged before the barrier, so the release store below (one
+        // write-back of this compute unit's L2 per block, not one per wave) publishes all of them
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+          __hip_atomic_store(F.done + wb, F.base + t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
   }
 }
 

@@ -61,9 +61,20 @@ void Launch<Q1, N>::step(lbsmrt_ctx* c, const StepArgs& A, const float* src, flo
   }
 
 template <int Q1, int N>
-template <int PREC, bool SH>
+template <int PREC, bool SH, int LPN, bool FLOW>
 const void* Launch<Q1, N>::persistent_fn() {
-    return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC>);
+    return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, SH, PREC, LPN, FLOW>);
+  }
+
+template <int Q1, int N>
+template <bool FLOW>
+const void* Launch<Q1, N>::persistent_flow(const lbsmrt_ctx* c) {
+    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8) return persistent_fn<kPrecFp64, true, 8, FLOW>();
+    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4) return persistent_fn<kPrecFp64, true, 4, FLOW>();
+    if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2) return persistent_fn<kPrecFp64, true, 2, FLOW>();
+    if (c->precision == LBSMRT_FP32)
+      return c->shock ? persistent_fn<kPrecFp32, true, 1, FLOW>() : persistent_fn<kPrecFp32, false, 1, FLOW>();
+    return c->shock ? persistent_fn<kPrecFp64, true, 1, FLOW>() : persistent_fn<kPrecFp64, false, 1, FLOW>();
   }
 
 template <int Q1, int N>
@@ -72,14 +83,7 @@ const void* Launch<Q1, N>::persistent(const lbsmrt_ctx* c) {
       return nullptr;
     } else {
       if (c->precision == LBSMRT_SPLIT_BF16X3) return nullptr;
-      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 8)
-        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 8>);
-      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 4)
-        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 4>);
-      if (c->precision == LBSMRT_FP64_CONTRACT && c->shock && c->lpn == 2)
-        return reinterpret_cast<const void*>(&k_collide_persistent<Q1, N, true, kPrecFp64, 2>);
-      if (c->precision == LBSMRT_FP32) return c->shock ? persistent_fn<kPrecFp32, true>() : persistent_fn<kPrecFp32, false>();
-      return c->shock ? persistent_fn<kPrecFp64, true>() : persistent_fn<kPrecFp64, false>();
+      return c->flow ? persistent_flow<true>(c) : persistent_flow<false>(c);
     }
   }
 

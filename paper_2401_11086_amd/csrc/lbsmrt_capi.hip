@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -110,7 +111,53 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_stage);
   (void)hipFree(c->d_ghost_m);
   (void)hipFree(c->d_mfma);
+  (void)hipFree(c->d_nbr);
+  (void)hipFree(c->d_done);
   delete c;
+}
+
+// Progress tables of the persistent launch on line domains for the current block table (blocks
+// of c->block / c->lpn nodes): each block depends on its neighbours in its domain (periodic rings
+// wrap), which must hold the whole pull reach max |e_j + k_x|.  False (and no tables) when a block
+// is shorter than the reach, or a ring of more than three blocks ends in a block shorter than the
+// reach (its neighbours would pull across it); the grid-barrier form is used then.
+bool build_flow(lbsmrt_ctx* c) {
+  (void)hipFree(c->d_nbr);
+  (void)hipFree(c->d_done);
+  c->d_nbr = nullptr;
+  c->d_done = nullptr;
+  int reach = 0;
+  for (int j = 0; j < c->Q1; ++j) reach = std::max(reach, std::abs(c->e1[j] + c->L.k[0]));
+  const int npb = c->block / c->lpn;
+  if (npb < reach) return false;
+  std::vector<int2> nbr;
+  for (const lbsmrt_domain& d : c->doms) {
+    const int nb = (d.nx + npb - 1) / npb;
+    const int b0 = static_cast<int>(nbr.size());
+    if (d.bc_x == 0 && nb > 3 && d.nx % npb != 0 && d.nx % npb < reach) return false;
+    for (int i = 0; i < nb; ++i) {
+      int prev = i > 0 ? b0 + i - 1 : -1, next = i + 1 < nb ? b0 + i + 1 : -1;
+      if (d.bc_x == 0 && nb > 1) {
+        if (prev < 0) prev = b0 + nb - 1;
+        if (next < 0) next = b0;
+      }
+      if (prev == next) next = -1;
+      nbr.push_back(int2{prev, next});
+    }
+  }
+  if (static_cast<int>(nbr.size()) != c->n_blocks) return false;
+  if (hipMalloc(&c->d_nbr, sizeof(int2) * nbr.size()) != hipSuccess ||
+      hipMalloc(&c->d_done, sizeof(unsigned) * nbr.size()) != hipSuccess ||
+      hipMemcpy(c->d_nbr, nbr.data(), sizeof(int2) * nbr.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->d_done, 0, sizeof(unsigned) * nbr.size()) != hipSuccess) {
+    (void)hipFree(c->d_nbr);
+    (void)hipFree(c->d_done);
+    c->d_nbr = nullptr;
+    c->d_done = nullptr;
+    return false;
+  }
+  c->flow_base = 0;
+  return true;
 }
 
 // Device address of scratch per device ordinal, looked up once per device with that device
@@ -211,6 +258,7 @@ const char* lbsmrt_status_string(lbsmrt_status s) {
     case LBSMRT_E_NOMEM: return "out of memory";
     case LBSMRT_E_UNSUPPORTED: return "unsupported configuration";
     case LBSMRT_E_LIMIT: return "problem too large for the fixed scratch of an allocation-free entry point";
+    case LBSMRT_E_TIMEOUT: return "a persistent launch's wait for a neighbouring work-group gave up";
   }
   return "unknown status";
 }
@@ -365,6 +413,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   bool lines = true;
   for (int i = 0; i < n_domains; ++i) lines = lines && domains[i].ny == 1 && domains[i].nz == 1;
   c->ms_lines = c->ms_ok && lines && !c->additive;
+  c->flow = false;   // set with the persistent launch (build_flow) for line domains
   c->ms_ok = c->ms_ok && !c->additive && (lines || (n_domains == 1 && domains[0].bc_x == 0));
   for (int t = 0; t <= p && t < kMsMaxTaps; ++t)
     for (int n = 0; n <= c->N; ++n) {
@@ -495,9 +544,11 @@ lbsmrt_status lbsmrt_step(lbsmrt_ctx* c, float* f_a, float* f_b, int n_steps, vo
     float* fb = f_b;
     int nb = c->n_blocks;
     int ns = n_steps;
-    void* args[] = {&L, &Ac, &fa, &fb, &nb, &ns};
+    FlowArgs F{c->d_nbr, c->d_done, c->flow_base, c->flow_spin_limit, c->flow_skew};
+    void* args[] = {&L, &Ac, &fa, &fb, &nb, &ns, &F};
     if (hipLaunchCooperativeKernel(fn, dim3(c->persistent_grid), dim3(c->block), args, 0, s) != hipSuccess)
       return LBSMRT_E_HIP;
+    if (c->flow) c->flow_base += static_cast<unsigned>(n_steps);
     return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
   }
   if (c->mode == LBSMRT_LAUNCH_GRAPH && n_steps >= 2 * c->graph_pairs) {
@@ -556,6 +607,9 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
     c->lpn = lpn;
   }
   if (mode == LBSMRT_LAUNCH_PERSISTENT) {
+    bool lines = true;
+    for (const lbsmrt_domain& d : c->doms) lines = lines && d.ny == 1 && d.nz == 1;
+    c->flow = lines && build_flow(c);
     const void* fn = nullptr;
     dispatch(c->Q1, c->N, [&](auto l) { fn = decltype(l)::persistent(c); });
     int per_cu = 0, cus = 0;
@@ -568,6 +622,13 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   }
   c->graph_pairs = mode == LBSMRT_LAUNCH_GRAPH ? graph_steps / 2 : 0;
   c->mode = mode;
+  return LBSMRT_OK;
+}
+
+lbsmrt_status lbsmrt_test_flow_wait(lbsmrt_ctx* c, unsigned spin_limit, unsigned skew) {
+  if (!c || spin_limit == 0) return LBSMRT_E_ARG;
+  c->flow_spin_limit = spin_limit;
+  c->flow_skew = skew;
   return LBSMRT_OK;
 }
 
@@ -764,7 +825,7 @@ lbsmrt_status lbsmrt_sync_status(lbsmrt_ctx* c, void* stream) {
   if (h != 0) {
     HIP_TRY(hipMemsetAsync(c->d_err, 0, sizeof(int), s));
     HIP_TRY(hipStreamSynchronize(s));
-    return LBSMRT_E_STATE;
+    return (h & kErrTimeout) ? LBSMRT_E_TIMEOUT : LBSMRT_E_STATE;
   }
   return LBSMRT_OK;
 }

@@ -224,3 +224,105 @@ def test_four_lanes_per_node_rejected_where_unsupported(torch):
     lat, fl, doms, fields, tau = _batch(torch, DRAWS)
     with pytest.raises(LbsmrtError):
         lat.set_launch("direct", 64, 64, 3)
+
+
+def _ring_lattice(torch, nxs):
+    """Periodic line domains (D3Q343, N = 4, no shift, pull reach 3) from a seeded perturbed
+    Maxwellian, in 64-node work-groups."""
+    from paper_2401_11086_amd import Lattice
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= 4}
+    doms = [dict(nx=n, ny=1, nz=1, bc_x=0) for n in nxs]
+    lat = Lattice([1, 2, 3], 9, 4, tau, doms, precision="fp64_contract")
+    lat.set_launch("direct", 64, 64, 1)
+    n = lat.n_nodes
+    fields = np.zeros((5, n))
+    x = np.arange(n)
+    fields[0] = 1.0 + 0.05 * np.sin(2 * np.pi * x / 37.0)
+    fields[1] = 0.1 * np.cos(2 * np.pi * x / 53.0)
+    fields[4] = 1.0 + 0.03 * np.sin(2 * np.pi * x / 29.0)
+    f0 = lat.equilibrium(torch.tensor(fields, dtype=torch.float64, device="cuda"))
+    f0[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=31), dtype=torch.float32, device="cuda")
+    return lat, f0
+
+
+# 320 = five full blocks (per-block progress); 257 = five blocks ending in one node, shorter than
+# the reach (grid barrier); 150, 128, 40 = rings of three, two and one block; 259 ends in three
+# nodes, as long as the reach (per-block progress) beside rings of four, three and one block
+@pytest.mark.parametrize("nxs", [[320], [257], [150, 128, 40], [256, 259, 130, 64]])
+def test_persistent_rings_match_direct_bitwise(torch, nxs):
+    lat, f0 = _ring_lattice(torch, nxs)
+    n = lat.n_nodes
+    ra, rb = lat.new_state(), lat.new_state()
+    ra.copy_(f0)
+    ref = lat.step(ra, rb, 17)
+    lat.sync()
+    lat.set_launch("persistent", 64, 4, 1)
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    for chunk in (5, 7, 5):                      # progress counters carried over calls
+        out = lat.step(fa, fb, chunk)
+        fa, fb = (out, fb if out is fa else fa)
+    lat.sync()
+    assert torch.equal(out[:, :n], ref[:, :n])
+    lat.close()
+
+
+def test_persistent_wait_give_up_is_reported(torch):
+    """Line batch in the persistent launch: with every wait's target made unreachable from the host
+    (and a short poll limit) the launch ends normally and lbsmrt_sync_status reports E_TIMEOUT;
+    restored, the next launches match the direct launch bitwise again."""
+    from paper_2401_11086_amd import _lib as C
+    from paper_2401_11086_amd._lib import LbsmrtError
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    f0 = lat.equilibrium(fl)
+    n = lat.n_nodes
+    ra, rb = lat.new_state(), lat.new_state()
+    ra.copy_(f0)
+    ref = lat.step(ra, rb, 6)
+    lat.sync()
+    lat.set_launch("persistent", 64, 4, 8)
+    C.check(C.lib().lbsmrt_test_flow_wait(lat._h, 16, 1 << 30), "lbsmrt_test_flow_wait")
+    ja, jb = lat.new_state(), lat.new_state()
+    ja.copy_(f0)
+    lat.step(ja, jb, 3)
+    with pytest.raises(LbsmrtError) as e:
+        lat.sync()
+    assert e.value.status == C.E_TIMEOUT
+    lat.sync()                                   # the status was cleared with the report
+    C.check(C.lib().lbsmrt_test_flow_wait(lat._h, 1 << 22, 0), "lbsmrt_test_flow_wait")
+    assert C.lib().lbsmrt_test_flow_wait(lat._h, 0, 0) == C.E_ARG
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    out = lat.step(fa, fb, 6)
+    lat.sync()
+    assert torch.equal(out[:, :n], ref[:, :n])
+
+
+def test_persistent_box_ignores_wait_hook(torch):
+    """A periodic box runs the persistent launch with the grid barrier: the wait hook changes nothing."""
+    from paper_2401_11086_amd import Lattice
+    from paper_2401_11086_amd import _lib as C
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= 4}
+    box = Lattice([1, 2, 3], 9, 4, tau, [dict(nx=16, ny=8, nz=8)], precision="fp64_contract")
+    f0 = box.equilibrium(torch.tensor(_box_fields(16, 8, 8), dtype=torch.float64, device="cuda"))
+    ra, rb = box.new_state(), box.new_state()
+    ra.copy_(f0)
+    ref = box.step(ra, rb, 4)
+    box.sync()
+    box.set_launch("persistent", 0, 4)
+    C.check(C.lib().lbsmrt_test_flow_wait(box._h, 16, 1 << 30), "lbsmrt_test_flow_wait")
+    fa, fb = box.new_state(), box.new_state()
+    fa.copy_(f0)
+    out = box.step(fa, fb, 4)
+    box.sync()
+    assert torch.equal(out, ref)
+
+
+def _box_fields(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    f = np.zeros((5, nz, ny, nx))
+    f[0] = 1.0 + 0.05 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny)
+    f[1] = 0.08 * np.sin(2 * np.pi * z / nz)
+    f[2] = 0.05 * np.cos(2 * np.pi * x / nx)
+    f[4] = 1.0 + 0.02 * np.cos(2 * np.pi * (x / nx + z / nz))
+    return f.reshape(5, -1)
