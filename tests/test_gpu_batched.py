@@ -326,3 +326,25 @@ def _box_fields(nx, ny, nz):
     f[2] = 0.05 * np.cos(2 * np.pi * x / nx)
     f[4] = 1.0 + 0.02 * np.cos(2 * np.pi * (x / nx + z / nz))
     return f.reshape(5, -1)
+
+
+@pytest.mark.parametrize("block,lpn", [(64, 8), (128, 1)])
+def test_persistent_q729_shocks_match_direct_bitwise(torch, block, lpn):
+    """D3Q729 (N = 5, shift 2: pull reach 7) shock batch in the persistent launch with per-block
+    progress, from a perturbed state: bitwise equal to direct launches after 11 steps."""
+    lat, fl, doms, fields, tau = _batch(torch, [(3.0, 45), (1.5, 70), (4.5, 33)], ab=(1, 2, 3, 5), deg=11, N=5, k=2)
+    lat.set_launch("direct", block, 64, lpn)
+    f0 = lat.equilibrium(fl)
+    n = lat.n_nodes
+    f0[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=29), dtype=torch.float32, device="cuda")
+    ra, rb = lat.new_state(), lat.new_state()
+    ra.copy_(f0)
+    ref = lat.step(ra, rb, 11)
+    lat.sync()
+    lat.set_launch("persistent", block, 4, lpn)
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    out = lat.step(fa, fb, 11)
+    lat.sync()
+    assert torch.equal(out[:, :n], ref[:, :n])
+    lat.close()
