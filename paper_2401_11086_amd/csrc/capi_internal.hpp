@@ -49,8 +49,7 @@ struct lbsmrt_ctx {
   // persistent launch on line domains: per-block progress instead of a grid-wide barrier
   bool flow = false;                 // every domain a line (ny = nz = 1)
   int2* d_nbr = nullptr;             // [n_blocks] the blocks each block pulls from (-1: none)
-  unsigned* d_done = nullptr;        // [n_blocks] steps completed, counted from flow_base
-  unsigned flow_base = 0;
+  unsigned* d_done = nullptr;        // [n_blocks] steps completed since the tables were built
   unsigned flow_spin_limit = 1u << 22;
   unsigned flow_skew = 0;
   hipGraphExec_t graph = nullptr;    // captured pair of steps for LBSMRT_LAUNCH_GRAPH

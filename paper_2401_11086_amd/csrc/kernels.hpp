@@ -842,17 +842,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   collide_stream_node<Q1, N, SHOCK, PREC, LPN, ADD>(L, A, fsrc, fdst, -1);
 }
 
-// Per-block progress of the persistent launch on line domains: nbr[b] = the blocks b depends on
-// (the neighbouring blocks of its domain within the pull reach, -1 for none), done[b] = the
-// number of steps block b has completed, counted from `base` (monotonic over calls, compared with
-// wrap-around), spin_limit = polls before a wait gives up.
 // s_waitcnt immediate of gfx9 waiting for vmcnt = 0 only (expcnt 7, lgkmcnt 15 left open).
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// Per-block progress of the persistent launch on line domains: nbr[b] = the blocks b depends on
+// (the neighbouring blocks of its domain within the pull reach, -1 for none), done[b] = the
+// number of steps block b has completed (since the tables were built; compared with
+// wrap-around), spin_limit = polls before a wait gives up.
 struct FlowArgs {
   const int2* nbr;
   unsigned* done;
-  unsigned base;
   unsigned spin_limit;
   unsigned skew;   // added to every wait's target: 0, or (tests of the give-up path) unreachable
 };
@@ -895,6 +894,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       grid.sync();
     }
   } else {
+    // Every launch takes every block through all its steps and the counters start equal, so all
+    // blocks hold the same count when a launch starts: each work-group reads it from its first
+    // block (written only by itself, and by earlier launches).  Counting from there, the launch
+    // depends on no step count kept by the host.
+    if (static_cast<int>(blockIdx.x) >= n_blocks) return;
+    unsigned base = 0;
+    if (threadIdx.x == 0) base = __hip_atomic_load(F.done + blockIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int t = 0; t < n_steps; ++t) {
       const float* src = (t & 1) ? fb : fa;
       float* dst = (t & 1) ? fa : fb;
@@ -902,8 +908,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (t > 0) {
           if (threadIdx.x == 0) {
             const int2 nb = F.nbr[wb];
-            wait_block(F, nb.x, F.base + F.skew + t, A.err);
-            wait_block(F, nb.y, F.base + F.skew + t, A.err);
+            wait_block(F, nb.x, base + F.skew + t, A.err);
+            wait_block(F, nb.y, base + F.skew + t, A.err);
             // pairs with the neighbours' release stores; the barrier orders the other waves'
             // loads after it (they share this work-item's compute unit and caches)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -912,11 +918,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         collide_stream_node<Q1, N, SHOCK, PREC, LPN>(L, A, src, dst, wb);
         // every wave's stores acknowledged before the barrier, so the release store below (one
-        // write-back of this compute unit's L2 per block, not one per wave) publishes all of them
+        // write-back of this XCD's L2 per block, not one per wave) publishes all of them
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
         if (threadIdx.x == 0)
-          __hip_atomic_store(F.done + wb, F.base + t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(F.done + wb, base + t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }

@@ -156,7 +156,6 @@ bool build_flow(lbsmrt_ctx* c) {
     c->d_done = nullptr;
     return false;
   }
-  c->flow_base = 0;
   return true;
 }
 
@@ -544,11 +543,10 @@ lbsmrt_status lbsmrt_step(lbsmrt_ctx* c, float* f_a, float* f_b, int n_steps, vo
     float* fb = f_b;
     int nb = c->n_blocks;
     int ns = n_steps;
-    FlowArgs F{c->d_nbr, c->d_done, c->flow_base, c->flow_spin_limit, c->flow_skew};
+    FlowArgs F{c->d_nbr, c->d_done, c->flow_spin_limit, c->flow_skew};
     void* args[] = {&L, &Ac, &fa, &fb, &nb, &ns, &F};
     if (hipLaunchCooperativeKernel(fn, dim3(c->persistent_grid), dim3(c->block), args, 0, s) != hipSuccess)
       return LBSMRT_E_HIP;
-    if (c->flow) c->flow_base += static_cast<unsigned>(n_steps);
     return hipGetLastError() == hipSuccess ? LBSMRT_OK : LBSMRT_E_HIP;
   }
   if (c->mode == LBSMRT_LAUNCH_GRAPH && n_steps >= 2 * c->graph_pairs) {

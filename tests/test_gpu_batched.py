@@ -348,3 +348,26 @@ def test_persistent_q729_shocks_match_direct_bitwise(torch, block, lpn):
     lat.sync()
     assert torch.equal(out[:, :n], ref[:, :n])
     lat.close()
+
+
+def test_persistent_interleaved_with_direct_launches(torch):
+    """Persistent launches on a shock batch, then direct ones, then persistent again (the progress
+    tables rebuilt): 5 + 4 + 6 steps bitwise equal to 15 direct steps."""
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    f0 = lat.equilibrium(fl)
+    n = lat.n_nodes
+    f0[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=33), dtype=torch.float32, device="cuda")
+    ra, rb = lat.new_state(), lat.new_state()
+    ra.copy_(f0)
+    ref = lat.step(ra, rb, 15)
+    lat.sync()
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    cur, other = fa, fb
+    for mode, k in (("persistent", 5), ("direct", 4), ("persistent", 6)):
+        lat.set_launch(mode, 64, 4, 8)
+        out = lat.step(cur, other, k)
+        cur, other = (out, other if out is cur else cur)
+    lat.sync()
+    assert torch.equal(cur[:, :n], ref[:, :n])
+    lat.close()
