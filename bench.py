@@ -159,15 +159,27 @@ def cpu_baseline(torch, ab, deg, N, edge, kn, sample_edge=32, steps=30):
 
 
 def cpu_model():
-    """The host CPU's model name (first processor in /proc/cpuinfo), or None."""
+    """The host CPU as /proc/cpuinfo names it (first processor: model name, family, model,
+    stepping), with the logical CPUs this process may run on, or None."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
     except OSError:
-        pass
-    return None
+        return None
+    if "model name" not in fields:
+        return None
+    ident = ", ".join(f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = None
+    where = f"; {avail} of {os.cpu_count()} logical CPUs available to this process" if avail else ""
+    return f"{fields['model name']} ({ident}{where})"
 
 
 def shock_samples(torch):
