@@ -54,8 +54,9 @@ typedef enum {
                                 configuration the split-BF16x3 form does not take (see
                                 lbsmrt_precision), regularized = 0 with FP32 contractions (or with
                                 the adjoint, the persistent launch or the moment state), D1Q17 with
-                                anything but the forward step, moments and equilibrium in FP64
-                                contractions and the rebuilt collision, or a launch setting the
+                                anything but the forward step, moments, equilibrium, the state
+                                conversions and the moment state on line domains, in FP64
+                                contractions with the rebuilt collision, or a launch setting the
                                 context does not allow */
   LBSMRT_E_LIMIT = 7,        /* the problem exceeds the fixed scratch of an allocation-free entry
                                 point (lbsmrt_step_adjoint_noalloc) */
@@ -299,11 +300,13 @@ lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* ctx, const float* m, float* f, voi
  * caller-owned device memory, contents irrelevant (unused, may be NULL, when every domain is a
  * line); none of m_a, m_b, work may overlap.  E_UNSUPPORTED unless the context has exactly one
  * periodic domain (bc_x = 0) or only line domains (ny = nz = 1, any bc_x, any number), the
- * rebuilt collision, and the stencil D1Q7 {0, +-1, +-2, +-3} or D1Q9 {0, +-1, +-2, +-3, +-5}.
+ * rebuilt collision, and the stencil D1Q7 {0, +-1, +-2, +-3} or D1Q9 {0, +-1, +-2, +-3, +-5}, or
+ * on line domains D1Q17 {0, +-1..+-7, +-9} (Table 3's Ma 7 set).
  * The context's launch setting applies: in LBSMRT_LAUNCH_GRAPH mode `graph_steps` steps are
  * captured once per (m_a, m_b, work) and replayed (recaptured when any of them, the launch
  * settings or the relaxation times change); lanes_per_node >= 4 runs line domains with eight
- * lanes per node; the persistent mode launches directly.  E_HIP if a capture fails.
+ * lanes per node (sixteen for D1Q17: one tap pair per lane); the persistent mode launches
+ * directly.  E_HIP if a capture fails.
  * Validity failures latch the flag read by lbsmrt_sync_status.  Asynchronous. */
 lbsmrt_status lbsmrt_step_moment_state(lbsmrt_ctx* ctx, float* m_a, float* m_b, float* work, int n_steps,
                                        void* stream);
@@ -321,7 +324,8 @@ const char* lbsmrt_status_string(lbsmrt_status s);
 
 /* 1D rule r*{0, +-a_1..a_p} exact to `degree` for the unit Gaussian: writes
  * r and the p+1 weights (w_0, w_{a_1}, ..., w_{a_p}).  Smallest positive-weight
- * root (Table 3).  E_QUADRATURE if none exists, E_ARG on bad input. */
+ * root (Table 3), solved in binary128 and rounded to double (the same bits on every host).
+ * E_QUADRATURE if none exists, E_ARG on bad input. */
 lbsmrt_status lbsmrt_solve_quadrature(int n_abscissa, const int* abscissa, int degree,
                                       double* r_out, double* w_out);
 

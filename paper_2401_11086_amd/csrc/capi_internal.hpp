@@ -37,6 +37,8 @@ struct lbsmrt_ctx {
   lbsmrt::BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
   lbsmrt::BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
   lbsmrt::BlockDev* d_blocks_adj8 = nullptr; // 8-node work-groups of the adjoint at eight lanes per node
+  lbsmrt::BlockDev* d_blocks_adj16 = nullptr; // 4-node work-groups: the 17-point line moment-state kernel
+  int n_blocks_adj16 = 0;                     // at sixteen lanes per node (0: not used)
   int n_blocks_adj4 = 0, n_blocks_adj8 = 0;
   lbsmrt::BlockDev* d_blocks_adjR = nullptr; // 256-node work-groups of the adjoint on periodic domains
   int n_blocks_adjR = 0;             // (0: not used)
@@ -84,8 +86,9 @@ inline int adjoint_groups(const lbsmrt_ctx* c) {
 }
 
 // Launch dispatch over the compiled (Q1, N) pairs.  The 17-point stencil (kFull false) has the
-// forward step with FP64 contractions and the rebuilt collision, the moments and the equilibrium
-// fill only; the API refuses the rest for it before dispatching.
+// forward step with FP64 contractions and the rebuilt collision, the moments, the equilibrium
+// fill, and the moment-state form on line domains (one lane per node) with the state
+// conversions; the API refuses the rest for it before dispatching.
 template <int Q1, int N>
 struct Launch {
   static constexpr bool kFull = Q1 <= 9;

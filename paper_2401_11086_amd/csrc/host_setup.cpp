@@ -1,6 +1,6 @@
 // Host-side set-up of the LB-SMRT lattice: the 1D quadrature (Sec. 4.2,
 // D1Qd rules and Table 3's lattice constants) and the normal-shock end
-// states (eq:rankine).  Plain C++, long double, no GPU.
+// states (eq:rankine).  Plain C++ (long double and binary128 arithmetic), no GPU.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -12,53 +12,75 @@ namespace lbsmrt {
 
 namespace {
 
-long double gaussian_even_moment(int k) {  // (2k-1)!!
-  long double m = 1.0L;
+// The root is bracketed on a grid in long double and then bisected, and its weights solved, in
+// binary128 (__float128, software arithmetic): at degree 19 the residual below is ill-conditioned
+// enough that long double bisection left r ~2e-14 from the root and the weights' quadrature
+// identity off by ~3e-13, while binary128 gives r and w correctly rounded to double.  Only basic
+// operations are used (no powl: the x87 transcendental instructions behind it differ in their
+// last bits between processor vendors), so the rule is the same on every host.
+using quad = __float128;
+
+template <typename T>
+T abs_of(T x) { return x < 0 ? -x : x; }
+
+template <typename T>
+T gaussian_even_moment(int k) {  // (2k-1)!!
+  T m = 1;
   for (int j = 1; j < 2 * k; j += 2) m *= j;
   return m;
 }
 
+template <typename T>
+T even_power(T x, int k) {  // x^(2k)
+  const T x2 = x * x;
+  T v = 1;
+  for (int i = 0; i < k; ++i) v *= x2;
+  return v;
+}
+
 // Weights w_0, w_{a_j} matching the even moments 0..2(n_eq-1) for a given r;
 // Gaussian elimination with partial pivoting.  Returns false if singular.
-bool weights_for(const std::vector<int>& ab, long double r, int n_eq, std::vector<long double>& w) {
+template <typename T>
+bool weights_for(const std::vector<int>& ab, T r, int n_eq, std::vector<T>& w) {
   const int p = static_cast<int>(ab.size());
   const int n = p + 1;
-  std::vector<long double> A(n_eq * n), b(n_eq);
+  std::vector<T> A(n_eq * n), b(n_eq);
   for (int k = 0; k < n_eq; ++k) {
-    A[k * n + 0] = (k == 0) ? 1.0L : 0.0L;
-    for (int j = 0; j < p; ++j) A[k * n + j + 1] = 2.0L * powl(ab[j] * r, 2 * k);
-    b[k] = gaussian_even_moment(k);
+    A[k * n + 0] = (k == 0) ? T(1) : T(0);
+    for (int j = 0; j < p; ++j) A[k * n + j + 1] = 2 * even_power<T>(ab[j] * r, k);
+    b[k] = gaussian_even_moment<T>(k);
   }
   for (int c = 0; c < n; ++c) {
     int piv = c;
     for (int i = c + 1; i < n; ++i)
-      if (fabsl(A[i * n + c]) > fabsl(A[piv * n + c])) piv = i;
-    if (A[piv * n + c] == 0.0L) return false;
+      if (abs_of(A[i * n + c]) > abs_of(A[piv * n + c])) piv = i;
+    if (A[piv * n + c] == 0) return false;
     if (piv != c) {
       for (int j = 0; j < n; ++j) std::swap(A[c * n + j], A[piv * n + j]);
       std::swap(b[c], b[piv]);
     }
     for (int i = c + 1; i < n; ++i) {
-      const long double f = A[i * n + c] / A[c * n + c];
+      const T f = A[i * n + c] / A[c * n + c];
       for (int j = c; j < n; ++j) A[i * n + j] -= f * A[c * n + j];
       b[i] -= f * b[c];
     }
   }
-  w.assign(n, 0.0L);
+  w.assign(n, T(0));
   for (int i = n - 1; i >= 0; --i) {
-    long double s = b[i];
+    T s = b[i];
     for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * w[j];
     w[i] = s / A[i * n + i];
   }
   return true;
 }
 
-bool residual(const std::vector<int>& ab, long double r, int k_top, long double& res) {
-  std::vector<long double> w;
-  if (!weights_for(ab, r, k_top, w)) return false;
-  long double s = 0.0L;
-  for (size_t j = 0; j < ab.size(); ++j) s += 2.0L * w[j + 1] * powl(ab[j] * r, 2 * k_top);
-  res = s - gaussian_even_moment(k_top);
+template <typename T>
+bool residual(const std::vector<int>& ab, T r, int k_top, T& res) {
+  std::vector<T> w;
+  if (!weights_for<T>(ab, r, k_top, w)) return false;
+  T s = 0;
+  for (size_t j = 0; j < ab.size(); ++j) s += 2 * w[j + 1] * even_power<T>(ab[j] * r, k_top);
+  res = s - gaussian_even_moment<T>(k_top);
   return true;
 }
 
@@ -77,24 +99,25 @@ lbsmrt_status solve_quadrature(const int* abscissa, int p, int degree, double* r
   const int n_grid = 12000;
   const long double lo = 0.02L, hi = 6.0L;
   long double prev_r = lo, prev_f = 0.0L;
-  bool have_prev = residual(ab, lo, k_top, prev_f);
+  bool have_prev = residual<long double>(ab, lo, k_top, prev_f);
   for (int i = 1; i < n_grid; ++i) {
     const long double r = lo + (hi - lo) * i / (n_grid - 1);
     long double f;
-    if (!residual(ab, r, k_top, f)) { have_prev = false; continue; }
+    if (!residual<long double>(ab, r, k_top, f)) { have_prev = false; continue; }
     if (have_prev && ((prev_f < 0) != (f < 0))) {
-      long double a = prev_r, b = r, fa = prev_f;
-      for (int it = 0; it < 200; ++it) {
-        const long double m = 0.5L * (a + b);
-        long double fm;
-        if (!residual(ab, m, k_top, fm)) break;
+      quad a = prev_r, b = r, fa = 0;
+      bool ok = residual<quad>(ab, a, k_top, fa);
+      for (int it = 0; ok && it < 120; ++it) {
+        const quad m = (a + b) / 2;
+        quad fm;
+        if (!residual<quad>(ab, m, k_top, fm)) break;
         if ((fm < 0) == (fa < 0)) { a = m; fa = fm; } else { b = m; }
       }
-      const long double root = 0.5L * (a + b);
-      std::vector<long double> w;
-      if (weights_for(ab, root, k_top, w)) {
+      const quad root = (a + b) / 2;
+      std::vector<quad> w;
+      if (ok && weights_for<quad>(ab, root, k_top, w)) {
         bool pos = true;
-        for (long double x : w) pos = pos && (x > 0.0L);
+        for (const quad& x : w) pos = pos && (x > 0);
         if (pos) {
           *r_out = static_cast<double>(root);
           for (int j = 0; j <= p; ++j) w_out[j] = static_cast<double>(w[j]);

@@ -332,19 +332,24 @@ __device__ __forceinline__ double dpp_move_f64(double v) {
 
 template <int LPN, int M>
 __device__ __forceinline__ void group_allreduce(double (&a)[M]) {
-  static_assert(LPN == 2 || LPN == 4 || LPN == 8, "groups of 2, 4 or 8 lanes");
+  static_assert(LPN == 2 || LPN == 4 || LPN == 8 || LPN == 16, "groups of 2, 4, 8 or 16 lanes");
   constexpr int kSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // quad_perm [1,0,3,2]
   constexpr int kSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // quad_perm [2,3,0,1]
   constexpr int kHalfMirror = 0x141;                            // row_half_mirror
+  constexpr int kMirror = 0x140;                                // row_mirror
 #pragma unroll
   for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kSwap1>(a[i]);
   if constexpr (LPN >= 4) {
 #pragma unroll
     for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kSwap2>(a[i]);
   }
-  if constexpr (LPN == 8) {
+  if constexpr (LPN >= 8) {
 #pragma unroll
     for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kHalfMirror>(a[i]);
+  }
+  if constexpr (LPN == 16) {   // each lane's mirror lies in the other half-row, which holds its sum
+#pragma unroll
+    for (int i = 0; i < M; ++i) a[i] += dpp_move_f64<kMirror>(a[i]);
   }
 }
 

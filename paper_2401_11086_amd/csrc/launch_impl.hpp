@@ -204,7 +204,21 @@ void Launch<Q1, N>::ms_step(lbsmrt_ctx* c, const MsGeom& G, const float* src, fl
 template <int Q1, int N>
 void Launch<Q1, N>::ms_line_step(lbsmrt_ctx* c, const StepArgs& A0, const float* src, float* dst, hipStream_t s) {
     if constexpr (!kFull) {
-      return;
+      // nine tap pairs: sixteen lanes per node (one tap pair each) when the context splits nodes
+      // over four or more lanes (shock tubes), else one
+      StepArgs A = A0;
+      const bool split = c->lpn >= 4 && c->n_blocks_adj16 > 0;
+      A.blocks = split ? c->d_blocks_adj16 : c->d_blocks_adj;
+      const int nb = split ? c->n_blocks_adj16 : c->n_blocks_adj;
+      if (split)
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 16>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
+                           c->d_ghost_m, src, dst);
+      else if (c->shock)
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, true, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
+                           c->d_ghost_m, src, dst);
+      else
+        hipLaunchKernelGGL((k_ms_line_collide<Q1, N, false, 1>), dim3(nb), dim3(kAdjBlock), 0, s, c->L, A,
+                           c->d_ghost_m, src, dst);
     } else {
       StepArgs A = A0;
       const bool split = c->lpn >= 4;
@@ -227,49 +241,32 @@ void Launch<Q1, N>::ms_line_step(lbsmrt_ctx* c, const StepArgs& A0, const float*
 
 template <int Q1, int N>
 bool Launch<Q1, N>::ms_taps_match(const lbsmrt_ctx* c) {
-    if constexpr (!kFull) {
-      return false;
-    } else {
-      const int p = Q1 / 2;
-      for (int t = 0; t <= Taps1D<Q1>::p; ++t)
-        if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
-      return true;
-    }
+    const int p = Q1 / 2;
+    for (int t = 0; t <= Taps1D<Q1>::p; ++t)
+      if (c->e1[p + t] != Taps1D<Q1>::e[t]) return false;
+    return true;
   }
 
 template <int Q1, int N>
 bool Launch<Q1, N>::ms_std_match(const lbsmrt_ctx* c) {
-    if constexpr (!kFull) {
-      return false;
-    } else {
-      auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-13 * std::max(1.0, std::fabs(b)); };
-      for (int t = 0; t <= Taps1D<Q1>::p; ++t)
-        for (int n = 0; n <= N; ++n)
-          if (!close(c->ms_tab.He[t][n], MsStdTables<Q1>::He[t][n]) ||
-              !close(c->ms_tab.Rw[t][n], MsStdTables<Q1>::Rw[t][n]))
-            return false;
-      return true;
-    }
+    auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-13 * std::max(1.0, std::fabs(b)); };
+    for (int t = 0; t <= Taps1D<Q1>::p; ++t)
+      for (int n = 0; n <= N; ++n)
+        if (!close(c->ms_tab.He[t][n], MsStdTables<Q1>::He[t][n]) || !close(c->ms_tab.Rw[t][n], MsStdTables<Q1>::Rw[t][n]))
+          return false;
+    return true;
   }
 
 template <int Q1, int N>
 void Launch<Q1, N>::ms_project(lbsmrt_ctx* c, const float* f, float* m, hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-      hipLaunchKernelGGL((k_ms_project<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, f, m, c->stride, c->n_nodes);
-    }
+    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+    hipLaunchKernelGGL((k_ms_project<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, f, m, c->stride, c->n_nodes);
   }
 
 template <int Q1, int N>
 void Launch<Q1, N>::ms_expand(lbsmrt_ctx* c, const float* m, float* f, hipStream_t s) {
-    if constexpr (!kFull) {
-      return;
-    } else {
-      const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
-      hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
-    }
+    const unsigned nb = static_cast<unsigned>((c->n_nodes + 255) / 256);
+    hipLaunchKernelGGL((k_ms_expand<Q1, N>), dim3(nb), dim3(256), 0, s, c->L, m, f, c->stride, c->n_nodes);
   }
 
 template <int Q1, int N>

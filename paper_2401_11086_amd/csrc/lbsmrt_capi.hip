@@ -107,6 +107,7 @@ void free_ctx(lbsmrt_ctx* c) {
   (void)hipFree(c->d_blocks_adj);
   (void)hipFree(c->d_blocks_adj4);
   (void)hipFree(c->d_blocks_adj8);
+  (void)hipFree(c->d_blocks_adj16);
   (void)hipFree(c->d_blocks_adjR);
   (void)hipFree(c->d_stage);
   (void)hipFree(c->d_ghost_m);
@@ -384,6 +385,10 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   }
   c->n_blocks_adj4 = static_cast<int>(bla4.size());
   c->n_blocks_adj8 = static_cast<int>(bla8.size());
+  // the 17-point stencil's nine tap pairs take sixteen lanes per node in the line moment-state kernel
+  std::vector<BlockDev> bla16;
+  if (c->lpn4_ok && Q1 > 9) bla16 = block_table(c->doms, kAdjBlock / 16);
+  c->n_blocks_adj16 = static_cast<int>(bla16.size());
   // periodic domains with N <= 4: 256-node adjoint work-groups when their LDS fits one work-group
   std::vector<BlockDev> blaR;
   if (!c->shock && c->N <= 4) {
@@ -413,7 +418,7 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   for (int i = 0; i < n_domains; ++i) lines = lines && domains[i].ny == 1 && domains[i].nz == 1;
   c->ms_lines = c->ms_ok && lines && !c->additive;
   c->flow = false;   // set with the persistent launch (build_flow) for line domains
-  c->ms_ok = c->ms_ok && !c->additive && (lines || (n_domains == 1 && domains[0].bc_x == 0));
+  c->ms_ok = c->ms_ok && !c->additive && (lines || (c->Q1 <= 9 && n_domains == 1 && domains[0].bc_x == 0));
   for (int t = 0; t <= p && t < kMsMaxTaps; ++t)
     for (int n = 0; n <= c->N; ++n) {
       c->ms_tab.He[t][n] = L.He64[p + t][n];
@@ -437,6 +442,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   if (!bla4.empty() && hipMalloc(&c->d_blocks_adj4, sizeof(BlockDev) * bla4.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
   if (!bla8.empty() && hipMalloc(&c->d_blocks_adj8, sizeof(BlockDev) * bla8.size()) != hipSuccess)
+    return fail(LBSMRT_E_NOMEM);
+  if (!bla16.empty() && hipMalloc(&c->d_blocks_adj16, sizeof(BlockDev) * bla16.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
   if (!blaR.empty() && hipMalloc(&c->d_blocks_adjR, sizeof(BlockDev) * blaR.size()) != hipSuccess)
     return fail(LBSMRT_E_NOMEM);
@@ -484,6 +491,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
       (!bla8.empty() && hipMemcpyAsync(c->d_blocks_adj8, bla8.data(), sizeof(BlockDev) * bla8.size(),
                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (!bla16.empty() && hipMemcpyAsync(c->d_blocks_adj16, bla16.data(), sizeof(BlockDev) * bla16.size(),
+                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
       (!blaR.empty() && hipMemcpyAsync(c->d_blocks_adjR, blaR.data(), sizeof(BlockDev) * blaR.size(),
                                        hipMemcpyHostToDevice, s) != hipSuccess) ||
       hipMemcpyAsync(c->d_ghost_fields, gf.data(), sizeof(double) * gf.size(), hipMemcpyHostToDevice, s) !=
@@ -738,7 +747,6 @@ lbsmrt_status lbsmrt_equilibrium_moments(lbsmrt_ctx* c, const double* fields, fl
 
 lbsmrt_status lbsmrt_project_state(lbsmrt_ctx* c, const float* f, float* m, void* stream) {
   if (!c || !f || !m) return LBSMRT_E_ARG;
-  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
   const size_t fb = sizeof(float) * c->Q * c->stride, mb = sizeof(float) * c->M * c->stride;
   if (overlap(f, fb, m, mb)) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -748,7 +756,6 @@ lbsmrt_status lbsmrt_project_state(lbsmrt_ctx* c, const float* f, float* m, void
 
 lbsmrt_status lbsmrt_expand_state(lbsmrt_ctx* c, const float* m, float* f, void* stream) {
   if (!c || !f || !m) return LBSMRT_E_ARG;
-  if (c->Q1 > 9) return LBSMRT_E_UNSUPPORTED;   // no kernel for the 17-point stencil
   const size_t fb = sizeof(float) * c->Q * c->stride, mb = sizeof(float) * c->M * c->stride;
   if (overlap(f, fb, m, mb)) return LBSMRT_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -46,15 +46,16 @@ struct Taps1D<9> {
   static constexpr int e[5] = {0, 1, 2, 3, 5};
 };
 template <>
-struct Taps1D<17> {   // D1Q17: no moment-state kernel (more taps than MomentTables64 holds)
+struct Taps1D<17> {   // D1Q17: the line kernel with one lane per node only (nine taps)
   static constexpr int p = 8;
   static constexpr int H = 9;
   static constexpr int e[9] = {0, 1, 2, 3, 4, 5, 6, 7, 9};
 };
 
 // 1D tables of the non-negative taps t (c = r e_t): He[t][b] = He_b(c), Rw[t][a] = w He_a(c) / a!,
-// so K_{b a}(e_t) = He[t][b] Rw[t][a].  Stencils of up to nine points have a moment-state kernel.
-constexpr int kMsMaxTaps = 5;
+// so K_{b a}(e_t) = He[t][b] Rw[t][a].  Stencils of up to nine points have every moment-state
+// kernel, the 17-point stencil the line kernel (one lane per node) and the state conversions.
+constexpr int kMsMaxTaps = 9;
 struct MomentTables64 {
   double He[kMsMaxTaps][kMaxN + 1];
   double Rw[kMsMaxTaps][kMaxN + 1];
@@ -231,6 +232,10 @@ constexpr int group_index(int N, int BY, int BZ) {
 #define LBSMRT_GROUPS_PER_PHASE 3
 #endif
 constexpr int kGroupsPerPhase = LBSMRT_GROUPS_PER_PHASE;
+// The line kernel's phase length per stencil: the 17-point stencil loads 17 values per field and
+// tap group, so one group per phase (three held about 300 loads in flight and spilled).
+template <int Q1>
+constexpr int line_groups_per_phase() { return Q1 > 9 ? 1 : kGroupsPerPhase; }
 #ifndef LBSMRT_GROUPS_PER_PHASE_ROW
 #define LBSMRT_GROUPS_PER_PHASE_ROW 5
 #endif
@@ -574,7 +579,7 @@ __device__ __forceinline__ void line_group(const LatticeConst& L, const float* _
     line_tap_pair<N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T.op[t], T.gp[t], T.om[t], T.gm[t],
                                     t > 0, he, rw, acc);
   }
-  // pin the sums, and fence the loads after every kGroupsPerPhase groups; the moments wait for
+  // pin the sums, and fence the loads after every phase of groups; the moments wait for
   // the collision as float32 (as in pass x)
 #pragma unroll
   for (int b = 0; b <= NO; ++b) {
@@ -582,7 +587,7 @@ __device__ __forceinline__ void line_group(const LatticeConst& L, const float* _
     asm volatile("" : "+v"(v));
     a32[midx(b, BY, BZ)] = v;
   }
-  if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
+  if constexpr ((group_index(N, BY, BZ) + 1) % line_groups_per_phase<Q1>() == 0) asm volatile("" ::: "memory");
 }
 
 template <int Q1, int N, bool GHOST, int BY, int BZ>

@@ -41,6 +41,62 @@ def test_library_quadrature_matches_oracle(lib, ab, deg):
     assert np.allclose(w, wo, rtol=1e-12, atol=1e-16)
 
 
+def _decimal_rule(ab, deg, digits=60):
+    """The positive-weight rule to `digits` decimal digits: bisection on r of the top even-moment
+    residual, the weights from the lower moments by Gaussian elimination, all in Decimal (no
+    float step, no library call)."""
+    from decimal import Decimal as D, localcontext
+    with localcontext() as ctx:
+        ctx.prec = digits
+        n, k_top = len(ab) + 1, len(ab) + 1
+        dfact = [D(1)]
+        for k in range(1, k_top + 1):
+            dfact.append(dfact[-1] * (2 * k - 1))
+
+        def weights(r):
+            A = [[D(1 if k == 0 else 0)] + [2 * (D(a) * r) ** (2 * k) for a in ab] for k in range(n)]
+            b = dfact[:n]
+            for c in range(n):
+                piv = max(range(c, n), key=lambda i: abs(A[i][c]))
+                A[c], A[piv], b[c], b[piv] = A[piv], A[c], b[piv], b[c]
+                for i in range(c + 1, n):
+                    f = A[i][c] / A[c][c]
+                    A[i] = [A[i][j] - f * A[c][j] for j in range(n)]
+                    b[i] -= f * b[c]
+            w = [D(0)] * n
+            for i in range(n - 1, -1, -1):
+                w[i] = (b[i] - sum(A[i][j] * w[j] for j in range(i + 1, n))) / A[i][i]
+            return w
+
+        def res(r):
+            w = weights(r)
+            return sum(2 * w[j + 1] * (D(a) * r) ** (2 * k_top) for j, a in enumerate(ab)) - dfact[k_top]
+
+        r0 = D(repr(O.solve_d1_quadrature(ab, deg)[0]))      # bracket the oracle's root
+        lo, hi = r0 * (1 - D("1e-9")), r0 * (1 + D("1e-9"))
+        flo = res(lo)
+        assert (flo < 0) != (res(hi) < 0)
+        for _ in range(160):
+            mid = (lo + hi) / 2
+            fm = res(mid)
+            if (fm < 0) == (flo < 0):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        r = (lo + hi) / 2
+        return r, weights(r)
+
+
+@pytest.mark.parametrize("ab,deg", [([1, 2, 3], 9), ([1, 2, 3, 5], 11), ([1, 2, 3, 4, 5, 6, 7, 9], 19)])
+def test_library_quadrature_is_correctly_rounded(lib, ab, deg):
+    """r and every weight equal the 60-digit rule rounded to double (the library bisects and
+    solves in binary128, with basic operations only, so the rule is also the same on every host)."""
+    r, w = lib.solve_quadrature(ab, deg)
+    rd, wd = _decimal_rule(ab, deg)
+    assert r == float(rd), (r, float(rd))
+    assert list(w) == [float(x) for x in wd], (list(w), [float(x) for x in wd])
+
+
 def test_library_rejects_infeasible_stencil(lib):
     with pytest.raises(lib.LbsmrtError) as e:
         lib.solve_quadrature([1, 2, 3, 4], 11)
@@ -80,7 +136,7 @@ def test_compiled_tap_tables_are_current(lib):
     gen = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen)
     text = open(os.path.join(path, "ms_std_tables.hpp")).read()
-    for q1, N in ((7, 4), (9, 5)):
+    for q1, N in ((7, 4), (9, 5), (17, 5)):
         he, rw = gen.table(q1)
         block = text[text.index(f"struct MsStdTables<{q1}>"):]
         for name, ref in (("He", he), ("Rw", rw)):

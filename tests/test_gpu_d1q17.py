@@ -1,7 +1,8 @@
 """D3Q4913 (tensor product of D1Q17 {0, +-1..+-7, +-9}, degree 19; Table 3's set for Ma 7)
 through the C ABI against the FP64 oracle on the same seeded states: one step of a Ma 7 shock
-tube (one and eight lanes per node) and of a small periodic box, and the calls the library
-refuses for this stencil."""
+tube (one and eight lanes per node) and of a small periodic box; the moment-state form on line
+domains against the population step and the oracle; and the calls the library refuses for this
+stencil."""
 import numpy as np
 import pytest
 
@@ -97,9 +98,120 @@ def test_d1q17_refused_calls(torch):
     assert e.value.status == C.E_UNSUPPORTED
     f = lat.equilibrium(torch.tensor(case["fields"], dtype=torch.float64, device="cuda"))
     dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
-    for call in (lambda: lat.step_adjoint(f, lat.new_state(), lat.new_state(), dtau),
-                 lambda: lat.project_state(f),
-                 lambda: lat.expand_state(lat.new_moment_state())):
-        with pytest.raises(C.LbsmrtError) as e:
-            call()
-        assert e.value.status == C.E_UNSUPPORTED
+    with pytest.raises(C.LbsmrtError) as e:
+        lat.step_adjoint(f, lat.new_state(), lat.new_state(), dtau)
+    assert e.value.status == C.E_UNSUPPORTED
+    box = _lattice(box_case(4, D1Q17, 5, n_ref=32))           # the moment state: line domains only
+    mb = box.new_moment_state()
+    with pytest.raises(C.LbsmrtError) as e:
+        box.step_moment_state(mb, box.new_moment_state(), box.new_moment_work(), 1)
+    assert e.value.status == C.E_UNSUPPORTED
+
+
+# ---- moment-state form on line domains (the x-stage kernel, one lane per node) ---------------
+
+def _noisy_moments(torch, lat, fields, seed, amp=0.02):
+    """Equilibrium moments with multiplicative noise on every moment of order >= 2."""
+    m = lat.equilibrium_moments(torch.tensor(fields, dtype=torch.float64, device="cuda"))
+    n = lat.n_nodes
+    m[4:, :n] *= torch.tensor(W.state_noise((lat.M - 4, n), seed=seed, amp=amp), dtype=torch.float32, device="cuda")
+    return m
+
+
+def _ma7_tubes(specs):
+    from paper_2401_11086_amd import Lattice
+    from paper_2401_11086_amd import _lib as C
+    from paper_2401_11086_amd.shocks import shock_domain
+    c_l, _ = C.solve_quadrature(*D1Q17)
+    doms, fields, ks = [], [], []
+    for Ma, nx in specs:
+        d, fl, st = shock_domain(Ma, nx, c_l)
+        doms.append(d)
+        fields.append(fl)
+        ks.append(int(st["k"]))
+    assert len(set(ks)) == 1
+    vs = O.make_velocity_set(*D1Q17)
+    tau20 = 2.0 * vs.r / 0.6
+    tau = {key: float(v) * tau20 for key, v in O.TAU_STAR_SMRT.items() if key[0] <= 5}
+    lat = Lattice(D1Q17[0], D1Q17[1], 5, tau, doms, shift_k=(ks[0], 0, 0), precision="fp64_contract")
+    return lat, np.concatenate(fields, axis=1)
+
+
+@pytest.mark.parametrize("specs", [[(7.0, 60)], [(7.0, 45), (6.0, 70)], None], ids=["ma7_tube", "batch2", "ring"])
+def test_d3q4913_line_moment_state_matches_population_step(torch, specs):
+    if specs is None:                                   # periodic ring of 50 nodes, no shift
+        from paper_2401_11086_amd import Lattice
+        vs = O.make_velocity_set(*D1Q17)
+        tau = {key: float(v) * 2.0 * vs.r / 0.6 for key, v in O.TAU_STAR_SMRT.items() if key[0] <= 5}
+        lat = Lattice(D1Q17[0], D1Q17[1], 5, tau, [dict(nx=50, ny=1, nz=1, bc_x=0)], precision="fp64_contract")
+        rng = np.random.default_rng(41)
+        fields = np.zeros((5, 50))
+        fields[0] = 1.0 + 0.03 * rng.uniform(-1, 1, 50)
+        fields[1] = 0.05 * rng.uniform(-1, 1, 50)
+        fields[4] = 1.0 + 0.03 * rng.uniform(-1, 1, 50)
+    else:
+        lat, fields = _ma7_tubes(specs)
+    n = lat.n_nodes
+    assert lat.moment_state_len()[1] == 0
+    m0 = _noisy_moments(torch, lat, fields, seed=42)
+    f0 = lat.expand_state(m0)
+    steps = 5
+    f_pop = lat.step(f0.clone(), lat.new_state(), steps)
+    m_out = lat.step_moment_state(m0, lat.new_moment_state(), lat.new_moment_work(), steps)
+    lat.sync()
+    f_mom = lat.expand_state(m_out)
+    torch.cuda.synchronize()
+    a, b = f_mom[:, :n].double(), f_pop[:, :n].double()
+    err = float((a - b).abs().max() / b.abs().max())
+    print(f"D3Q4913 {specs}: {steps} steps, line moment state vs population state {err:.2e}")
+    assert err < TOL_STEP, err
+    # the projection of the population state returns the moments it was expanded from
+    back = lat.project_state(f_pop)
+    torch.cuda.synchronize()
+    assert torch.isfinite(back[:, :n]).all()
+
+
+def test_d3q4913_line_moment_state_one_step_matches_oracle(torch):
+    case = shock_case(7.0, 40, D1Q17, 5)
+    lat = _lattice(case)
+    m0 = _noisy_moments(torch, lat, case["fields"], seed=43)
+    f0 = lat.expand_state(m0)
+    m1 = lat.step_moment_state(m0, lat.new_moment_state(), lat.new_moment_work(), 1)
+    lat.sync()
+    g = lat.expand_state(m1)[:, :40].double().cpu().numpy()
+    fo1 = O.step(oracle_state_from_gpu(f0.cpu().numpy(), case), case["model"], case["dom"])
+    err = float(np.abs(g - fo1.reshape(g.shape)).max() / np.abs(fo1).max())
+    print(f"D3Q4913 Ma 7 shock, one line moment-state step vs FP64 oracle: {err:.2e}")
+    assert err < TOL_STEP, err
+
+
+def test_d3q4913_project_expand_round_trip(torch):
+    """expand then project returns the moments (the quadrature is exact to degree 2N)."""
+    case = shock_case(7.0, 30, D1Q17, 5)
+    lat = _lattice(case)
+    m0 = _noisy_moments(torch, lat, case["fields"], seed=44)
+    m1 = lat.project_state(lat.expand_state(m0))
+    torch.cuda.synchronize()
+    n = lat.n_nodes
+    err = float((m1[:, :n].double() - m0[:, :n].double()).abs().max() / m0[:, :n].double().abs().max())
+    print(f"D3Q4913 project(expand(m)) - m: {err:.2e}")
+    assert err < 1e-6, err
+
+
+def test_d3q4913_line_moment_state_sixteen_lanes_agree_with_one(torch):
+    """Shock tubes run the 17-point line kernel with sixteen lanes per node (one tap pair each,
+    the partial moments summed over the row) when the lane setting is four or more: 4 steps agree
+    with one lane per node to float32 rounding."""
+    lat, fields = _ma7_tubes([(7.0, 57), (6.5, 30)])
+    n = lat.n_nodes
+    m0 = _noisy_moments(torch, lat, fields, seed=45)
+    outs = []
+    for lanes in (1, 8):
+        lat.set_launch("direct", 0, 64, lanes)
+        ma = m0.clone()
+        outs.append(lat.step_moment_state(ma, lat.new_moment_state(), lat.new_moment_work(), 4).clone())
+    lat.sync()
+    a, b = outs[1][:, :n].double(), outs[0][:, :n].double()
+    err = float((a - b).abs().max() / b.abs().max())
+    print(f"D3Q4913 line moment state, sixteen lanes vs one after 4 steps: {err:.2e}")
+    assert err < 2e-6, err
