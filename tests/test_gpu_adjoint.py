@@ -126,7 +126,7 @@ def test_loss_and_gradient_through_many_steps_match_oracle(torch):
             f = O.step(f, m, case["dom"])
         return O.shock_loss(f, m, case["dom"], tgt, scales)
     L_o = float(np.real(oracle_loss(tau0)))
-    assert abs(float(L) - L_o) <= 1e-4 * L_o, (float(L), L_o)
+    assert abs(float(L.detach()) - L_o) <= 1e-4 * L_o, (float(L.detach()), L_o)
     g_o = []
     for k in keys:
         t = dict(tau0)
