@@ -275,6 +275,13 @@ def copy_calibration(torch, n_floats, steps, warmup):
                       "bytes_per_launch": 8 * n_floats, "ms_per_copy": round(ms, 4), "steps": steps}), flush=True)
 
 
+def adjoint_pair(lat, f, lam_a, lam_b, dtau):
+    """Two adjoint steps, each taking the other's output (timed as a dependent chain, as a reverse
+    sweep runs them)."""
+    lat.step_adjoint(f, lam_a, lam_b, dtau)
+    lat.step_adjoint(f, lam_b, lam_a, dtau)
+
+
 def _time_steps(torch, fn, n):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -296,7 +303,7 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     for other in [p for p in PRECISIONS if p != args.precision]:
         lat2 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision=other)
         lat2.step(fa, fb, 2)
-        ms = _time_steps(torch, lambda: lat2.step(fa, fb, 1), steps)
+        ms = _time_steps(torch, lambda: lat2.step(fa, fb, steps), 1) / steps
         lat2.sync()
         rec = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2),
                "hbm_frac": round(8.0 * lat.Q * lat.n_nodes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -309,7 +316,7 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     lat3 = Lattice(ab, deg, N, tau, [dict(nx=edge, ny=edge, nz=edge, bc_x=0)], precision="fp64_contract",
                    regularized=False)
     lat3.step(fa, fb, 2)
-    ms = _time_steps(torch, lambda: lat3.step(fa, fb, 1), steps)
+    ms = _time_steps(torch, lambda: lat3.step(fa, fb, steps), 1) / steps
     lat3.sync()
     lat3.close()
     out["additive_collision"] = {"ms_per_step": round(ms, 4), "mlups": round(lat.n_nodes / (ms / 1e3) / 1e6, 2),
@@ -320,7 +327,7 @@ def time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_fwd):
     lam_a.normal_()
     dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
     lat.step_adjoint(fa, lam_a, lam_b, dtau)
-    ms_adj = _time_steps(torch, lambda: lat.step_adjoint(fa, lam_a, lam_b, dtau), steps)
+    ms_adj = _time_steps(torch, lambda: adjoint_pair(lat, fa, lam_a, lam_b, dtau), max(2, steps // 2)) / 2
     lat.sync()
     assert torch.isfinite(dtau).all()
     _progress(f"adjoint: {ms_adj:.3f} ms/step ({ms_adj / ms_fwd:.2f}x forward)")
@@ -420,22 +427,22 @@ def time_shock_adjoint(torch, steps=300):
     fa = lat.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda"))
     fb = lat.new_state()
     lat.step(fa, fb, 10)
-    ms_fwd = _time_steps(torch, lambda: lat.step(fa, fb, 1), steps)
+    ms_fwd = _time_steps(torch, lambda: lat.step(fa, fb, steps), 1) / steps
     ma, mb, work = lat.project_state(fa), lat.new_moment_state(), lat.new_moment_work()
     lat.step_moment_state(ma, mb, work, 10)
-    ms_mom = _time_steps(torch, lambda: lat.step_moment_state(ma, mb, work, 1), steps)
+    ms_mom = _time_steps(torch, lambda: lat.step_moment_state(ma, mb, work, steps), 1) / steps
     lam_a, lam_b = lat.new_state(), lat.new_state()
     lam_a.normal_()
     dtau = torch.zeros(18, dtype=torch.float64, device="cuda")
     lat.step_adjoint(fa, lam_a, lam_b, dtau)
-    ms_adj = _time_steps(torch, lambda: lat.step_adjoint(fa, lam_a, lam_b, dtau), steps)
+    ms_adj = _time_steps(torch, lambda: adjoint_pair(lat, fa, lam_a, lam_b, dtau), steps // 2) / 2
     lat.sync()
     assert torch.isfinite(dtau).all()
     lat.close()
     lat_b = Lattice(ab, deg, N, tau, [d], shift_k=(2, 0, 0), precision="split_bf16x3")
     ga, gb = lat_b.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda")), lat_b.new_state()
     lat_b.step(ga, gb, 10)
-    ms_b = _time_steps(torch, lambda: lat_b.step(ga, gb, 1), steps)
+    ms_b = _time_steps(torch, lambda: lat_b.step(ga, gb, steps), 1) / steps
     lat_b.sync()
     lat_b.close()
     _progress(f"shock adjoint (Nx 600, D3Q729): forward {ms_fwd * 1e3:.1f} us (moment state {ms_mom * 1e3:.1f} us, "
@@ -443,6 +450,32 @@ def time_shock_adjoint(torch, steps=300):
     return {"workload": "Ma 3 shock, Nx 600, D3Q729, N=5, FP64 contractions", "forward_us": round(ms_fwd * 1e3, 2),
             "forward_moment_state_us": round(ms_mom * 1e3, 2), "forward_split_bf16x3_us": round(ms_b * 1e3, 2),
             "adjoint_us": round(ms_adj * 1e3, 2), "ratio_to_forward": round(ms_adj / ms_fwd, 3)}
+
+
+def time_shock_d3q4913(torch, steps=200):
+    """Table 3's Ma 7 set D3Q4913 (D1Q17, degree 19, k = 3) on a 400-cell tube: the population
+    step (eight lanes per node) against the moment-state step (sixteen lanes per node)."""
+    from paper_2401_11086_amd import Lattice, solve_quadrature
+    from paper_2401_11086_amd.shocks import shock_domain
+    ab, deg, N = [1, 2, 3, 4, 5, 6, 7, 9], 19, 5
+    c_l, _ = solve_quadrature(ab, deg)
+    d, f, st = shock_domain(7.0, 400, c_l)
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= N}
+    lat = Lattice(ab, deg, N, tau, [d], shift_k=(int(st["k"]), 0, 0), precision="fp64_contract")
+    fa = lat.equilibrium(torch.tensor(f, dtype=torch.float64, device="cuda"))
+    fb = lat.new_state()
+    lat.step(fa, fb, 10)
+    ms_pop = _time_steps(torch, lambda: lat.step(fa, fb, steps), 1) / steps
+    ma, mb, work = lat.project_state(fa), lat.new_moment_state(), lat.new_moment_work()
+    lat.step_moment_state(ma, mb, work, 10)
+    ms_mom = _time_steps(torch, lambda: lat.step_moment_state(ma, mb, work, steps), 1) / steps
+    lat.sync()
+    launch = lat.launch_settings()
+    lat.close()
+    _progress(f"Ma 7 tube on D3Q4913 (400 cells): population {ms_pop * 1e3:.1f} us, moment state {ms_mom * 1e3:.1f} us")
+    return {"workload": "Ma 7 shock, Nx 400, D3Q4913 (D1Q17 degree 19), N=5, FP64 contractions",
+            "lanes_per_node_setting": launch["lanes_per_node"], "population_us": round(ms_pop * 1e3, 2),
+            "moment_state_us": round(ms_mom * 1e3, 2), "speedup": round(ms_pop / ms_mom, 2)}
 
 
 def time_batched(torch, n_shocks=64, steps=5000, seed=0):
@@ -555,9 +588,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=5000)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-contraction and adjoint timings")
-    ap.add_argument("--variants", default="moment_state,forms,shock_adjoint,batched",
+    ap.add_argument("--variants", default="moment_state,forms,shock_adjoint,d3q4913,batched",
                     help="comma list of the variant groups to time after the main step: moment_state, forms "
-                         "(other contraction forms, additive collision, adjoint), shock_adjoint, batched")
+                         "(other contraction forms, additive collision, adjoint), shock_adjoint, d3q4913, batched")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain device copy of one f buffer instead (HBM calibration)")
     args = ap.parse_args()
@@ -623,6 +656,8 @@ def main():
         variants.update(time_variants(torch, lat, fa, fb, ab, deg, N, tau, edge, args, ms_step))
     if "shock_adjoint" in groups:
         variants["shock_adjoint"] = time_shock_adjoint(torch)
+    if "d3q4913" in groups:
+        variants["shock_d3q4913"] = time_shock_d3q4913(torch)
     if "batched" in groups:
         variants["batched_mach_sweep"] = time_batched(torch, steps=args.batched_steps)
 
