@@ -604,52 +604,62 @@ __device__ __forceinline__ void line_groups(const LatticeConst& L, const float* 
   }
 }
 
-// Lanes per node: lane `sub` of a node's group takes the tap pair e_sub (the centre for sub = 0,
-// nothing for sub > p) for every group, and the group sums the partial moments with the DPP row
-// moves of the population kernel, so every lane holds the same sums and runs the same collision.
-template <int N>
-struct LaneTap {
-  unsigned op, om;
-  int gp, gm;
-  bool pair;                          // false for the centre tap (no -e partner)
-  double he[N + 1], rw[N + 1];        // He_b(c_t), Rw_a(c_t) of the lane's tap (zero beyond the taps)
-};
-
-template <int Q1, int N, bool GHOST, int BY, int BZ>
-__device__ __forceinline__ void line_group_lane(const float* __restrict__ src, long long stride,
-                                                const float* __restrict__ ghost_m, int n_ghost,
-                                                const LaneTap<N>& T, double (&d)[n_moments(N)]) {
+// One tap pair's contribution to group (BY, BZ), its two sources read from the work-group's
+// staged window (W slots per field, field-major) at slots wp (tap +e_t) and wm (tap -e_t);
+// he[b] = He_b(c_t), rw[a] = Rw_a(c_t) (FP64), pair false for the centre tap.
+template <int N, int W, int BY, int BZ>
+__device__ __forceinline__ void win_tap_pair(const float* win, int wp, int wm, bool pair,
+                                             const double (&he)[N + 1], const double (&rw)[N + 1], double* acc) {
   constexpr int NO = N - BY - BZ;
-  double acc[NO + 1];
+  double ev = 0.0, od = 0.0;   // rebuilt population folded: even part (for even b), odd part
 #pragma unroll
-  for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
-  line_tap_pair<N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T.op, T.gp, T.om, T.gm, T.pair, T.he,
-                                  T.rw, acc);
-#pragma unroll
-  for (int b = 0; b <= NO; ++b) {
-    asm volatile("" : "+v"(acc[b]));
-    d[midx(b, BY, BZ)] = acc[b];
+  for (int a = 0; a <= NO; ++a) {
+    const float* row = win + midx(a, BY, BZ) * W;
+    // fold in FP32: exact where the two sources agree (a uniform state stays uniform)
+    const float vp = row[wp];
+    const float vm = pair ? row[wm] : 0.f;
+    const double s = static_cast<double>(vp + vm), dd = static_cast<double>(vp - vm);
+    // K_{ba} uses s when a + b is even, d when odd
+    ev = fma(rw[a], (a & 1) ? dd : s, ev);
+    od = fma(rw[a], (a & 1) ? s : dd, od);
   }
-  if constexpr ((group_index(N, BY, BZ) + 1) % kGroupsPerPhase == 0) asm volatile("" ::: "memory");
+#pragma unroll
+  for (int b = 0; b <= NO; ++b) acc[b] = fma(he[b], (b & 1) ? od : ev, acc[b]);
 }
 
-template <int Q1, int N, bool GHOST, int BY, int BZ>
-__device__ __forceinline__ void line_groups_lane(const float* __restrict__ src, long long stride,
-                                                 const float* __restrict__ ghost_m, int n_ghost,
-                                                 const LaneTap<N>& T, double (&d)[n_moments(N)]) {
+// Group (BY, BZ) and the groups after it in their compile-time order, for one lane's tap pair
+// (its tables chosen at run time; zero beyond the taps) of the node at window slot wp - H + e.
+template <int N, int W, int BY, int BZ>
+__device__ __forceinline__ void win_groups_lane(const float* win, int wp, int wm, bool pair,
+                                                const double (&he)[N + 1], const double (&rw)[N + 1],
+                                                double (&d)[n_moments(N)]) {
   if constexpr (BY <= N) {
     if constexpr (BY + BZ <= N) {
-      line_group_lane<Q1, N, GHOST, BY, BZ>(src, stride, ghost_m, n_ghost, T, d);
-      line_groups_lane<Q1, N, GHOST, BY, BZ + 1>(src, stride, ghost_m, n_ghost, T, d);
+      constexpr int NO = N - BY - BZ;
+      double acc[NO + 1];
+#pragma unroll
+      for (int b = 0; b <= NO; ++b) acc[b] = 0.0;
+      win_tap_pair<N, W, BY, BZ>(win, wp, wm, pair, he, rw, acc);
+#pragma unroll
+      for (int b = 0; b <= NO; ++b) d[midx(b, BY, BZ)] = acc[b];
+      win_groups_lane<N, W, BY, BZ + 1>(win, wp, wm, pair, he, rw, d);
     } else {
-      line_groups_lane<Q1, N, GHOST, BY + 1, 0>(src, stride, ghost_m, n_ghost, T, d);
+      win_groups_lane<N, W, BY + 1, 0>(win, wp, wm, pair, he, rw, d);
     }
   }
 }
 
-// One node of a line domain per LPN work-items; work-groups of 64 work-items cover 64 / LPN nodes
-// of the block table (any number of line domains, each of its own length and end states).
-// ghost_m: float32 [M][n_ghost] moments of the end states (columns 2 d, 2 d + 1 for domain d).
+// One node of a line domain per LPN work-items; work-groups of 64 work-items cover G = 64 / LPN
+// consecutive nodes of one domain (a block of the block table; any number of line domains, each
+// of its own length and end states; ghost_m: float32 [M][n_ghost] moments of the end states,
+// columns 2 d, 2 d + 1 for domain d).
+// LPN = 1: each work-item loads its taps' sources itself, a few groups' loads in flight at a time.
+// LPN > 1 (short tubes, where each wave's serial load rounds set the step): the work-group first
+// stages every moment field at the G + 2 H source positions its nodes pull from (x - e - k,
+// |e| <= H) into LDS, one load per slot and eight in flight per work-item, with the periodic wrap
+// of rings and the end states past a tube's ends resolved there; each lane then reads its tap
+// pair from LDS.  (Staging with one lane per node was measured slower: 28.4 against 26.7 us on
+// the 64-shock sweep.)
 template <int Q1, int N, bool SHOCK, int LPN = 1>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 : 1))) void k_ms_line_collide(
     LatticeConst L, StepArgs A, const float* __restrict__ ghost_m, const float* __restrict__ src,
@@ -658,25 +668,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
   constexpr int M = n_moments(N);
   const BlockDev bd = A.blocks[blockIdx.x];
   const DomainDev D = A.doms[bd.dom];
-  const int x = bd.first + static_cast<int>(threadIdx.x) / LPN;
-  const int sub = static_cast<int>(threadIdx.x) % LPN;
-  if (x >= D.nx) return;                      // whole groups: the lanes of a node share x
   const int row0 = static_cast<int>(D.off);
-  bool ghost = false;
-  auto source = [&](int xs, unsigned& off, int& g) {
-    g = -1;
-    if (D.bc_x == 0) {
-      xs %= D.nx;
-      if (xs < 0) xs += D.nx;
-    } else if (xs < 0 || xs >= D.nx) {
-      g = D.ghost + (xs < 0 ? 0 : 1);
-      ghost = true;
-      xs = x;                                   // an in-domain address; the ghost value replaces it
-    }
-    off = static_cast<unsigned>(row0 + xs) * 4u;
-  };
+  const int xl = static_cast<int>(threadIdx.x) / LPN;
+  const int x = bd.first + xl;
   double d[M];
   if constexpr (LPN == 1) {
+    if (x >= D.nx) return;
+    bool ghost = false;
+    auto source = [&](int xs, unsigned& off, int& g) {
+      g = -1;
+      if (D.bc_x == 0) {
+        xs %= D.nx;
+        if (xs < 0) xs += D.nx;
+      } else if (xs < 0 || xs >= D.nx) {
+        g = D.ghost + (xs < 0 ? 0 : 1);
+        ghost = true;
+        xs = x;                                 // an in-domain address; the ghost value replaces it
+      }
+      off = static_cast<unsigned>(row0 + xs) * 4u;
+    };
     LineTaps<Q1> T;
 #pragma unroll
     for (int t = 0; t <= S::p; ++t) {
@@ -690,11 +700,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
     for (int i = 0; i < M; ++i) d[i] = static_cast<double>(a32[i]);
   } else {
     static_assert(LPN > S::p, "one tap pair per lane");
-    LaneTap<N> T;
+    constexpr int G = 64 / LPN;               // nodes per work-group
+    constexpr int W = G + 2 * S::H;           // staged source positions per field
+    __shared__ float win[M * W];
+    const int w0 = bd.first - S::H - L.k[0]; // position of slot 0
+    // source address of window slot i (field i / W)
+    auto slot = [&](int i) -> const float* {
+      const int f = i / W;
+      int pos = w0 + (i - f * W);
+      if (D.bc_x == 0 || !SHOCK) {
+        pos %= D.nx;
+        if (pos < 0) pos += D.nx;
+      } else if (pos < 0 || pos >= D.nx) {
+        return ghost_m + static_cast<size_t>(f) * A.n_ghost + D.ghost + (pos < 0 ? 0 : 1);
+      }
+      return src + static_cast<size_t>(f) * A.stride + row0 + pos;
+    };
+    constexpr int kIter = (M * W + 63) / 64;  // slots per work-item
+    constexpr int kBatch = 8;                  // loads in flight per work-item
+#pragma unroll 1
+    for (int it0 = 0; it0 < kIter; it0 += kBatch) {
+      float v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int i = (it0 + u) * 64 + static_cast<int>(threadIdx.x);
+        v[u] = (it0 + u < kIter && i < M * W) ? *slot(i) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int i = (it0 + u) * 64 + static_cast<int>(threadIdx.x);
+        if (it0 + u < kIter && i < M * W) win[i] = v[u];
+      }
+    }
+    __syncthreads();
+    if (x >= D.nx) return;                    // whole groups: the lanes of a node share x
+    const int sub = static_cast<int>(threadIdx.x) % LPN;
     const int t = sub <= S::p ? sub : 0;
     int e = S::e[0];
 #pragma unroll
     for (int j = 1; j <= S::p; ++j) e = t == j ? S::e[j] : e;
+    double he[N + 1], rw[N + 1];
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
       double h = tab_he<Q1>(0, n), r = tab_rw<Q1>(0, n);
@@ -703,14 +748,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N >= 5 ? 2 :
         h = t == j ? tab_he<Q1>(j, n) : h;
         r = t == j ? tab_rw<Q1>(j, n) : r;
       }
-      T.he[n] = sub <= S::p ? h : 0.0;          // lanes beyond the taps contribute nothing
-      T.rw[n] = r;
+      he[n] = sub <= S::p ? h : 0.0;          // lanes beyond the taps contribute nothing
+      rw[n] = r;
     }
-    T.pair = t > 0;
-    source(x - e - L.k[0], T.op, T.gp);
-    source(x + e - L.k[0], T.om, T.gm);
-    if (SHOCK && __any(ghost)) line_groups_lane<Q1, N, SHOCK, 0, 0>(src, A.stride, ghost_m, A.n_ghost, T, d);
-    else line_groups_lane<Q1, N, false, 0, 0>(src, A.stride, ghost_m, A.n_ghost, T, d);
+    win_groups_lane<N, W, 0, 0>(win, xl + S::H - e, xl + S::H + e, t > 0, he, rw, d);
     group_allreduce<LPN, M>(d);
   }
   double S5[5];
