@@ -134,7 +134,7 @@ def test_loss_and_gradient_through_many_steps_match_oracle(torch):
         g_o.append(oracle_loss(t).imag / H_CS)
     g_o = np.array(g_o)
     err = np.abs(g_gpu - g_o).max() / np.abs(g_o).max()
-    print(f"L gpu {float(L):.6e} oracle {L_o:.6e}; grad rel err {err:.2e}")
+    print(f"L gpu {float(L.detach()):.6e} oracle {L_o:.6e}; grad rel err {err:.2e}")
     assert err < 1e-3, (g_gpu, g_o)
 
 
