@@ -160,21 +160,22 @@ lbsmrt_status lbsmrt_get_domain_offsets(const lbsmrt_ctx* ctx, long long* out, i
 enum { LBSMRT_LAUNCH_DIRECT = 0, LBSMRT_LAUNCH_GRAPH = 1, LBSMRT_LAUNCH_PERSISTENT = 2 };
 
 /* Choose the launch mode, the work-group size (64, 128 or 256 work-items; 0 keeps the current
- * one) and the lanes per node of the step kernel (1, 2, 4 or 8; 0 keeps the current one).  With
+ * one) and the lanes per node of the step kernel (1, 2, 4, 8 or 16; 0 keeps the current one).  With
  * L > 1 lanes, a group of L consecutive work-items shares each node: each gathers and stores every
  * L-th x-slab of the node's populations and the group sums its moments before the (replicated)
  * collision, so a work-group of B work-items updates B/L nodes.  That shortens each wavefront's
  * serial work when a context has few nodes (single shock tubes).  Results do not depend on the
  * mode or the work-group size; lanes_per_node > 1 changes the order of the FP64 projection sums
  * (results agree with 1 to FP64 rounding before the FP32 store).  The adjoint step uses the
- * same split when lanes_per_node is 4 or 8 and one lane per node otherwise.  Synchronous.
+ * same split when lanes_per_node is 4, 8 or 16 and one lane per node otherwise.  Synchronous.
  * E_ARG for an unknown mode, size, lanes_per_node or odd graph_steps; E_UNSUPPORTED for
  * lanes_per_node > 1 unless the context has shock domains, LBSMRT_FP64_CONTRACT and a state
  * below 4 GiB (Q * f_stride * 4 bytes) and the rebuilt collision, for the persistent mode of an
- * additive-collision context, or if the persistent kernel cannot be made resident.
+ * additive-collision context or with sixteen lanes per node, or if the persistent kernel cannot
+ * be made resident.
  * A new context starts in direct mode with work-groups of 256 (64 if no domain reaches 4096
- * nodes) and one lane per node; an eligible context with at most 8192 nodes starts with eight,
- * one with at most 16384 nodes with four. */
+ * nodes) and one lane per node; an eligible context with at most 8192 nodes starts with eight
+ * (sixteen up to 4096 nodes for D1Q9 and D1Q17), one with at most 16384 nodes with four. */
 lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* ctx, int mode, int block_size, int graph_steps, int lanes_per_node);
 
 /* Test hook of the persistent launch's bounded waits on line domains: polls before a wait gives

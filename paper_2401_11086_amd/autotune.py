@@ -13,8 +13,8 @@ import os
 
 import torch
 
-CANDIDATES = [(mode, block, lpn) for lpn in (1, 2, 4, 8) for mode in ("direct", "graph", "persistent")
-              for block in (64, 128, 256)]
+CANDIDATES = [(mode, block, lpn) for lpn in (1, 2, 4, 8, 16) for mode in ("direct", "graph", "persistent")
+              for block in (64, 128, 256) if not (lpn == 16 and mode == "persistent")]
 
 
 def _candidates(lat):

@@ -280,6 +280,30 @@ __global__ __launch_bounds__(kReduceBlocks) void k_reduce_tau(const double* __re
   }
 }
 
+// The same column sums in one launch when the partials are few (rows <= kSmallReduceRows): work-item
+// t of one group sums rows t, t + 256, ... in that order, then one fixed tree.  (Small domains:
+// the two-stage form cost two launches of about 9 and 5 us beside a ~45 us adjoint step.)
+constexpr int kSmallReduceRows = 16 * kReduceBlocks;
+template <int N>
+__global__ __launch_bounds__(kReduceBlocks) void k_reduce_tau_rows(const double* __restrict__ partial, int rows,
+                                                                   double* __restrict__ out) {
+  constexpr int NT = n_tau_slots(N);
+  __shared__ double red[NT * kReduceBlocks];
+  double s[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) s[c] = 0.0;
+  for (int r = static_cast<int>(threadIdx.x); r < rows; r += kReduceBlocks) {
+#pragma unroll
+    for (int c = 0; c < NT; ++c) s[c] += partial[static_cast<size_t>(r) * NT + c];
+  }
+  block_sum_cols<NT>(s, red);
+  if (threadIdx.x == 0) {
+    for (int nn = 2; nn <= N; ++nn)
+      for (int mm = 0; 2 * mm <= nn; ++mm)
+        if (!(nn == 2 && mm == 1)) out[nn * 3 + mm] += s[tau_slot(nn, mm)];
+  }
+}
+
 // Seed of the adjoint for L = sum_x [s0^2 (rho - rho*)^2 + s1^2 (theta - theta*)^2 + s2^2 (q_x - q_x*)^2]
 // on the pre-collision moments of state f.  lam[i][x - s_i] = dL/dg_i(x); per-block partial of L.
 template <int Q1, int N, bool SHOCK>

@@ -37,8 +37,8 @@ struct lbsmrt_ctx {
   lbsmrt::BlockDev* d_blocks_adj = nullptr;  // 64-item work-groups for the adjoint and the loss seed
   lbsmrt::BlockDev* d_blocks_adj4 = nullptr; // 16-node work-groups of the adjoint at four lanes per node
   lbsmrt::BlockDev* d_blocks_adj8 = nullptr; // 8-node work-groups of the adjoint at eight lanes per node
-  lbsmrt::BlockDev* d_blocks_adj16 = nullptr; // 4-node work-groups: the 17-point line moment-state kernel
-  int n_blocks_adj16 = 0;                     // at sixteen lanes per node (0: not used)
+  lbsmrt::BlockDev* d_blocks_adj16 = nullptr; // 4-node work-groups at sixteen lanes per node: the adjoint
+  int n_blocks_adj16 = 0;                     // and the 17-point line moment-state kernel (0: not used)
   int n_blocks_adj4 = 0, n_blocks_adj8 = 0;
   lbsmrt::BlockDev* d_blocks_adjR = nullptr; // 256-node work-groups of the adjoint on periodic domains
   int n_blocks_adjR = 0;             // (0: not used)
@@ -82,6 +82,7 @@ namespace lbsmrt {
 // grid when the context has one, else the grid of its lanes-per-node setting.
 inline int adjoint_groups(const lbsmrt_ctx* c) {
   if (!c->shock && c->n_blocks_adjR > 0) return c->n_blocks_adjR;
+  if (c->lpn == 16) return c->n_blocks_adj16;
   return c->lpn == 8 ? c->n_blocks_adj8 : (c->lpn == 4 ? c->n_blocks_adj4 : c->n_blocks_adj);
 }
 

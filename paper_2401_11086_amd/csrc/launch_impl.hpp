@@ -23,7 +23,10 @@ void Launch<Q1, N>::step_p(lbsmrt_ctx* c, const StepArgs& A, const float* src, f
         return;
       }
     }
-    if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
+    if (PREC == kPrecFp64 && c->shock && c->lpn == 16)
+      hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 16>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
+                         A, src, dst);
+    else if (PREC == kPrecFp64 && c->shock && c->lpn == 8)
       hipLaunchKernelGGL((k_collide_stream<Q1, N, true, kPrecFp64, 8>), dim3(c->n_blocks), dim3(c->block), 0, s, c->L,
                          A, src, dst);
     else if (PREC == kPrecFp64 && c->shock && c->lpn == 4)
@@ -114,7 +117,10 @@ void Launch<Q1, N>::adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, 
           return;
         }
       }
-      if (c->shock && c->lpn == 8)
+      if (c->shock && c->lpn == 16)
+        hipLaunchKernelGGL((k_adjoint<Q1, N, true, 16>), dim3(nb), dim3(kAdjBlock),
+                           (adjoint_lds_bytes<N, 16, kAdjBlock>()), s, c->L, A, f_t, lam_next, lam_t, partial);
+      else if (c->shock && c->lpn == 8)
         hipLaunchKernelGGL((k_adjoint<Q1, N, true, 8>), dim3(nb), dim3(kAdjBlock), (adjoint_lds_bytes<N, 8, kAdjBlock>()),
                            s, c->L, A, f_t, lam_next, lam_t, partial);
       else if (c->shock && c->lpn == 4)
@@ -126,6 +132,10 @@ void Launch<Q1, N>::adjoint(lbsmrt_ctx* c, const StepArgs& A, const float* f_t, 
       else
         hipLaunchKernelGGL((k_adjoint<Q1, N, false>), dim3(nb), dim3(kAdjBlock), (adjoint_lds_bytes<N, 1, kAdjBlock>()),
                            s, c->L, A, f_t, lam_next, lam_t, partial);
+      if (nb <= kSmallReduceRows) {
+        hipLaunchKernelGGL((k_reduce_tau_rows<N>), dim3(1), dim3(kReduceBlocks), 0, s, partial, nb, A.dtau);
+        return;
+      }
       hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceBlocks), dim3(256), 0, s, partial, nb, n_tau_slots(N), stage);
       hipLaunchKernelGGL((k_reduce_tau<N>), dim3(1), dim3(kReduceBlocks), 0, s, stage, A.dtau);
     }
@@ -140,7 +150,8 @@ bool Launch<Q1, N>::allow_adjoint_lds() {
         return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)) ==
                hipSuccess;
       };
-      return raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true, 8>), adjoint_lds_bytes<N, 8, kAdjBlock>()) &&
+      return raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true, 16>), adjoint_lds_bytes<N, 16, kAdjBlock>()) &&
+             raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true, 8>), adjoint_lds_bytes<N, 8, kAdjBlock>()) &&
              raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true, 4>), adjoint_lds_bytes<N, 4, kAdjBlock>()) &&
              raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, true>), adjoint_lds_bytes<N, 1, kAdjBlock>()) &&
              raise(reinterpret_cast<const void*>(&k_adjoint<Q1, N, false>), adjoint_lds_bytes<N, 1, kAdjBlock>());

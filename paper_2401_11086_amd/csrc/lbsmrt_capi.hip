@@ -237,7 +237,8 @@ lbsmrt_status adjoint_launch(lbsmrt_ctx* c, const float* f_t, const float* lam_n
                              double* partial, double* stage, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   StepArgs A = step_args(c);
-  A.blocks = c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj);
+  A.blocks = c->lpn == 16 ? c->d_blocks_adj16
+             : (c->lpn == 8 ? c->d_blocks_adj8 : (c->lpn == 4 ? c->d_blocks_adj4 : c->d_blocks_adj));
   if (!c->shock && c->n_blocks_adjR > 0) A.blocks = c->d_blocks_adjR;
   A.dtau = dL_dtau;
   dispatch(c->Q1, c->N, [&](auto l) { decltype(l)::adjoint(c, A, f_t, lam_next, lam_t, partial, stage, s); });
@@ -373,7 +374,11 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   // (the split kernels address a slab by a 32-bit byte offset from the start of f)
   c->lpn4_ok = c->shock && c->precision == LBSMRT_FP64_CONTRACT && !c->additive &&
                static_cast<long long>(c->Q) * c->stride * 4 < (1LL << 32);
-  if (c->lpn4_ok) c->lpn = off * 8 <= kSplitWorkItems ? 8 : (off * 4 <= kSplitWorkItems ? 4 : 1);
+  // nine or more x-slabs: sixteen lanes (one slab each on nine lanes) while the work-items stay
+  // within kSplitWorkItems; seven slabs gain nothing beyond eight
+  if (c->lpn4_ok)
+    c->lpn = (Q1 >= 9 && off * 16 <= kSplitWorkItems) ? 16
+             : (off * 8 <= kSplitWorkItems ? 8 : (off * 4 <= kSplitWorkItems ? 4 : 1));
   std::vector<BlockDev> bl = block_table(c->doms, c->block / c->lpn);
   c->n_blocks = static_cast<int>(bl.size());
   std::vector<BlockDev> bla = block_table(c->doms, kAdjBlock);
@@ -385,9 +390,10 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
   }
   c->n_blocks_adj4 = static_cast<int>(bla4.size());
   c->n_blocks_adj8 = static_cast<int>(bla8.size());
-  // the 17-point stencil's nine tap pairs take sixteen lanes per node in the line moment-state kernel
+  // sixteen lanes per node: the adjoint, and the 17-point stencil's line moment-state kernel
+  // (nine tap pairs)
   std::vector<BlockDev> bla16;
-  if (c->lpn4_ok && Q1 > 9) bla16 = block_table(c->doms, kAdjBlock / 16);
+  if (c->lpn4_ok) bla16 = block_table(c->doms, kAdjBlock / 16);
   c->n_blocks_adj16 = static_cast<int>(bla16.size());
   // periodic domains with N <= 4: 256-node adjoint work-groups when their LDS fits one work-group
   std::vector<BlockDev> blaR;
@@ -409,7 +415,8 @@ lbsmrt_status lbsmrt_init_lattice(const lbsmrt_lattice_desc* desc, const lbsmrt_
     if (!ok) { free_ctx(c); return LBSMRT_E_HIP; }
   }
   const size_t partial_rows =
-      static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8, c->n_blocks_adjR}));
+      static_cast<size_t>(std::max({c->n_blocks_adj, c->n_blocks_adj4, c->n_blocks_adj8, c->n_blocks_adj16,
+                                    c->n_blocks_adjR}));
   c->n_ghost = 2 * n_domains;
   // moment-state form (lbsmrt_step_moment_state): the FP64 1D tables of the non-negative taps t,
   // K_{b a}(e_t) = He_b(c_t) Rw_a(c_t)
@@ -589,10 +596,12 @@ lbsmrt_status lbsmrt_set_launch(lbsmrt_ctx* c, int mode, int block_size, int gra
   if (block_size != 0 && block_size != 64 && block_size != 128 && block_size != 256) return LBSMRT_E_ARG;
   if (mode == LBSMRT_LAUNCH_GRAPH && (graph_steps < 2 || graph_steps > 4096 || (graph_steps & 1)))
     return LBSMRT_E_ARG;
-  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4 && lanes_per_node != 8)
+  if (lanes_per_node != 0 && lanes_per_node != 1 && lanes_per_node != 2 && lanes_per_node != 4 && lanes_per_node != 8 &&
+      lanes_per_node != 16)
     return LBSMRT_E_ARG;
   if (lanes_per_node > 1 && !c->lpn4_ok) return LBSMRT_E_UNSUPPORTED;
-  if (mode == LBSMRT_LAUNCH_PERSISTENT && (c->additive || c->Q1 > 9 || c->precision == LBSMRT_SPLIT_BF16X3))
+  if (mode == LBSMRT_LAUNCH_PERSISTENT && (c->additive || c->Q1 > 9 || c->precision == LBSMRT_SPLIT_BF16X3 ||
+                                           (lanes_per_node != 0 ? lanes_per_node : c->lpn) == 16))
     return LBSMRT_E_UNSUPPORTED;
   if (c->precision == LBSMRT_SPLIT_BF16X3 && block_size != 0 && block_size != 256) return LBSMRT_E_UNSUPPORTED;
   if (hipSetDevice(c->device) != hipSuccess) return LBSMRT_E_HIP;

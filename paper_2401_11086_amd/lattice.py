@@ -221,7 +221,7 @@ class Lattice:
 
     def set_launch(self, mode="direct", block_size=0, graph_steps=64, lanes_per_node=0):
         """mode: 'direct', 'graph' or 'persistent'; block_size 64/128/256 (0 keeps it);
-        lanes_per_node 1, 2, 4 or 8 (0 keeps it; > 1 for shock contexts with FP64 contractions).
+        lanes_per_node 1, 2, 4, 8 or 16 (0 keeps it; > 1 for shock contexts with FP64 contractions).
         See lbsmrt_set_launch in include/lbsmrt.h."""
         m = {"direct": C.LAUNCH_DIRECT, "graph": C.LAUNCH_GRAPH, "persistent": C.LAUNCH_PERSISTENT}[mode]
         C.check(C.lib().lbsmrt_set_launch(self._h, m, int(block_size), int(graph_steps), int(lanes_per_node)),

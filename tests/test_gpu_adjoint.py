@@ -170,10 +170,10 @@ def test_zero_misfit_gives_zero_loss_and_gradient(torch):
 
 
 @pytest.mark.parametrize("name", ["shock_q343_n4", "shock_q729_n5"])
-@pytest.mark.parametrize("lpn", [4, 8])
+@pytest.mark.parametrize("lpn", [4, 8, 16])
 def test_adjoint_split_lanes_match_one_lane(torch, name, lpn):
-    """The adjoint step with each node's slabs split over four or eight lanes against one lane per
-    node: same lam_t up to the order of the FP64 sums, same dL/dtau."""
+    """The adjoint step with each node's slabs split over four, eight or sixteen lanes against one
+    lane per node: same lam_t up to the order of the FP64 sums, same dL/dtau."""
     case = ADJ_CASES[name]()
     lat = _lattice(case)
     n = lat.n_nodes

@@ -144,7 +144,8 @@ def test_batched_shock_matches_oracle_one_step(torch):
 
 @pytest.mark.parametrize("mode,block,lpn", [("direct", 64, 4), ("direct", 256, 4), ("graph", 128, 4),
                                             ("persistent", 64, 4), ("direct", 128, 2), ("persistent", 256, 2),
-                                            ("direct", 64, 8), ("graph", 256, 8), ("persistent", 128, 8)])
+                                            ("direct", 64, 8), ("graph", 256, 8), ("persistent", 128, 8),
+                                            ("direct", 64, 16), ("graph", 256, 16)])
 def test_lanes_per_node(torch, mode, block, lpn):
     """lanes_per_node = 2, 4 or 8 (each node's x-slabs split over a group of lanes): 13 steps agree with
     lanes_per_node = 1 to float32 rounding (the FP64 projection sums run in another order), equal
@@ -175,10 +176,10 @@ def test_lanes_per_node(torch, mode, block, lpn):
     assert torch.equal(mom, mom_ref)
 
 
-@pytest.mark.parametrize("lpn", [4, 8])
+@pytest.mark.parametrize("lpn", [4, 8, 16])
 def test_split_lanes_q729_one_step_matches_oracle(torch, lpn):
-    """D3Q729, N = 5 (nine x-slabs over four lanes: 3, 2, 2, 2; over eight: 2, 1, ..., 1), one step
-    from a perturbed state."""
+    """D3Q729, N = 5 (nine x-slabs over four lanes: 3, 2, 2, 2; over eight: 2, 1, ..., 1; over
+    sixteen: one each on nine lanes, none on seven), one step from a perturbed state."""
     draws = [(3.0, 45), (1.5, 70)]
     lat, fl, doms, fields, tau = _batch(torch, draws, ab=(1, 2, 3, 5), deg=11, N=5, k=2)
     lat.set_launch("direct", 128, 64, lpn)
@@ -204,14 +205,19 @@ def test_split_lanes_q729_one_step_matches_oracle(torch, lpn):
 
 
 def test_default_lanes_per_node(torch):
-    """Shock contexts with FP64 contractions start with 8 lanes per node up to 8192 nodes, 4 up to
-    16384, then 1."""
+    """Shock contexts with FP64 contractions start with 8 lanes per node up to 8192 nodes (16 up to
+    4096 for nine or more x-slabs), 4 up to 16384, then 1."""
     lat, fl, doms, fields, tau = _batch(torch, DRAWS)
     assert lat.launch_settings() == {"mode": "direct", "block": 64, "lanes_per_node": 8}
     mid, _, _, _, _ = _batch(torch, [(1.5, 6000), (2.0, 6000)])
     assert mid.launch_settings() == {"mode": "direct", "block": 256, "lanes_per_node": 4}
     big, _, _, _, _ = _batch(torch, [(1.5, 9000), (2.0, 9000)])
     assert big.launch_settings() == {"mode": "direct", "block": 256, "lanes_per_node": 1}
+    # nine x-slabs (D3Q729): sixteen lanes up to 4096 nodes
+    q9, _, _, _, _ = _batch(torch, [(3.0, 600)], ab=(1, 2, 3, 5), deg=11, N=5, k=2)
+    assert q9.launch_settings()["lanes_per_node"] == 16
+    q9b, _, _, _, _ = _batch(torch, [(3.0, 3000), (2.0, 3000)], ab=(1, 2, 3, 5), deg=11, N=5, k=2)
+    assert q9b.launch_settings()["lanes_per_node"] == 8
 
 
 def test_four_lanes_per_node_rejected_where_unsupported(torch):
@@ -371,3 +377,14 @@ def test_persistent_interleaved_with_direct_launches(torch):
     lat.sync()
     assert torch.equal(cur[:, :n], ref[:, :n])
     lat.close()
+
+
+def test_sixteen_lanes_refused_for_the_persistent_launch(torch):
+    from paper_2401_11086_amd._lib import LbsmrtError
+    lat, fl, doms, fields, tau = _batch(torch, DRAWS)
+    lat.set_launch("direct", 64, 4, 16)
+    with pytest.raises(LbsmrtError):
+        lat.set_launch("persistent", 64, 4, 0)
+    with pytest.raises(LbsmrtError):
+        lat.set_launch("persistent", 64, 4, 16)
+    lat.set_launch("persistent", 64, 4, 8)

@@ -43,7 +43,7 @@ def test_d1q17_lattice_constant_is_table3():
     assert abs(vs.r - 0.5638701) < 5e-8
 
 
-@pytest.mark.parametrize("lanes", [1, 8])
+@pytest.mark.parametrize("lanes", [1, 8, 16])
 def test_d3q4913_ma7_shock_one_step_matches_oracle(torch, lanes):
     case = shock_case(7.0, 40, D1Q17, 5)
     lat = _lattice(case)

@@ -119,8 +119,9 @@ def test_autotune_candidates():
     tube64 = _FakeLattice([dict(nx=80, bc_x=1)], "fp64_contract")
     assert {c[2] for c in _candidates(box)} == {1}
     assert {c[2] for c in _candidates(tube32)} == {1}
-    assert {c[2] for c in _candidates(tube64)} == {1, 2, 4, 8}
-    assert len(_candidates(tube64)) == len(CANDIDATES) == 36
+    assert {c[2] for c in _candidates(tube64)} == {1, 2, 4, 8, 16}
+    assert not any(c[0] == "persistent" and c[2] == 16 for c in _candidates(tube64))
+    assert len(_candidates(tube64)) == len(CANDIDATES) == 42
 
 
 def test_autotune_key_separates_geometries(monkeypatch):
