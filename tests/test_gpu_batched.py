@@ -388,3 +388,42 @@ def test_sixteen_lanes_refused_for_the_persistent_launch(torch):
     with pytest.raises(LbsmrtError):
         lat.set_launch("persistent", 64, 4, 16)
     lat.set_launch("persistent", 64, 4, 8)
+
+
+def test_persistent_mixed_tubes_and_rings_match_direct_bitwise(torch):
+    """A shock context holding tubes and periodic rings (eight lanes per node, 8-node blocks):
+    the persistent launch with per-block progress equals direct launches bitwise after 12 steps."""
+    from paper_2401_11086_amd import Lattice, solve_quadrature
+    from paper_2401_11086_amd.shocks import shock_domain
+    c_l, _ = solve_quadrature([1, 2, 3], 9)
+    tau = {k: v for k, v in TAU_STAR.items() if k[0] <= 4}
+    d1, f1, _ = shock_domain(1.5, 70, c_l)
+    d2, f2, _ = shock_domain(2.2, 45, c_l)
+    rings = [dict(nx=64, ny=1, nz=1, bc_x=0), dict(nx=37, ny=1, nz=1, bc_x=0)]
+    ring_fields = []
+    for r in rings:
+        x = np.arange(r["nx"])
+        g = np.zeros((5, r["nx"]))
+        g[0] = 1.0 + 0.04 * np.sin(2 * np.pi * x / r["nx"])
+        g[1] = c_l * 1 + 0.05 * np.cos(2 * np.pi * x / r["nx"])    # around the frame velocity k = 1
+        g[4] = 1.0
+        ring_fields.append(g)
+    doms = [d1, rings[0], d2, rings[1]]
+    lat = Lattice([1, 2, 3], 9, 4, tau, doms, shift_k=(1, 0, 0), precision="fp64_contract")
+    fl = torch.tensor(np.concatenate([f1, ring_fields[0], f2, ring_fields[1]], axis=1), dtype=torch.float64,
+                      device="cuda")
+    lat.set_launch("direct", 64, 4, 8)
+    f0 = lat.equilibrium(fl)
+    n = lat.n_nodes
+    f0[:, :n] *= torch.tensor(W.state_noise((lat.Q, n), seed=37), dtype=torch.float32, device="cuda")
+    ra, rb = lat.new_state(), lat.new_state()
+    ra.copy_(f0)
+    ref = lat.step(ra, rb, 12)
+    lat.sync()
+    lat.set_launch("persistent", 64, 4, 8)
+    fa, fb = lat.new_state(), lat.new_state()
+    fa.copy_(f0)
+    out = lat.step(fa, fb, 12)
+    lat.sync()
+    assert torch.equal(out[:, :n], ref[:, :n])
+    lat.close()
